@@ -1,0 +1,298 @@
+"""FP64 CPU oracle for the plane-wave H psi, its adjoint, and block Davidson.
+
+TEST INFRASTRUCTURE ONLY: this package is used by ``tests/``, by the smoke
+check and by the benchmark's CPU-baseline leg. The GPU library never imports,
+links or calls it, and it shares no code with the GPU library; both only read
+the same seeded inputs.
+
+The arithmetic lives in ``oracle.c`` (own mixed-radix FFT, H psi, explicit H
+matrix, adjoint); this module loads it with ctypes and holds the block
+Davidson driver (``davidson``), written with numpy's dense linear algebra as
+its library steps.
+
+Problems are duck-typed: any object with the attributes of the generator's
+``Problem`` (lattice, fft, kpts, npw, miller, vloc, nproj, natom,
+proj_atom_offset, beta, dmat) works.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+
+
+def build(force: bool = False) -> str:
+    """Compile oracle.c with gcc into liboracle.so (plain -O2, OpenMP)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp"
+        subprocess.check_call(["gcc", "-O2", "-std=c11", "-fopenmp", "-fPIC", "-shared",
+                               _SRC, "-o", tmp, "-lm"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+class _Problem(C.Structure):
+    _fields_ = [
+        ("lattice", C.c_double * 9), ("fft", C.c_int * 3), ("nk", C.c_int),
+        ("kpts", C.c_void_p), ("npw", C.c_void_p), ("miller", C.c_void_p),
+        ("vloc", C.c_void_p), ("nproj", C.c_int), ("natom", C.c_int),
+        ("proj_atom_offset", C.c_void_p), ("beta", C.c_void_p), ("dmat", C.c_void_p),
+    ]
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        _lib = C.CDLL(build())
+        P = C.POINTER(_Problem)
+        vp, i, d = C.c_void_p, C.c_int, C.c_double
+        _lib.oracle_dft1d.argtypes = [i, i, vp, C.c_long, vp]
+        _lib.oracle_fft1d.argtypes = [i, i, vp, C.c_long, vp]
+        _lib.oracle_fft3d.argtypes = [vp, i, vp]
+        _lib.oracle_apply_h.argtypes = [P, i, vp, vp, i]
+        _lib.oracle_kinetic.argtypes = [P, i, vp]
+        _lib.oracle_dense_h.argtypes = [P, i, i, vp]
+        _lib.oracle_apply_h_backward.argtypes = [P, i, vp, vp, vp, vp, vp]
+        _lib.oracle_num_threads.restype = i
+    return _lib
+
+
+def _ptr(a):
+    return None if a is None else a.ctypes.data
+
+
+class _Bound:
+    """A C view of a problem that keeps every array it points to alive."""
+
+    def __init__(self, prob, vloc=None, dmat=None):
+        self.keep = [
+            np.ascontiguousarray(prob.kpts, dtype=np.float64),
+            np.ascontiguousarray(prob.npw, dtype=np.int32),
+            np.ascontiguousarray(prob.miller, dtype=np.int32),
+            np.ascontiguousarray(prob.vloc if vloc is None else vloc, dtype=np.float64),
+            np.ascontiguousarray(prob.proj_atom_offset, dtype=np.int32),
+            np.ascontiguousarray(prob.beta, dtype=np.complex128),
+            np.ascontiguousarray(prob.dmat if dmat is None else dmat, dtype=np.float64),
+        ]
+        s = _Problem()
+        s.lattice[:] = [float(x) for x in np.asarray(prob.lattice, dtype=np.float64).reshape(-1)]
+        s.fft[:] = [int(x) for x in prob.fft]
+        s.nk = int(len(prob.npw))
+        s.kpts, s.npw, s.miller, s.vloc, s.proj_atom_offset, s.beta, s.dmat = [_ptr(a) for a in self.keep]
+        s.nproj, s.natom = int(prob.nproj), int(prob.natom)
+        self.s = s
+
+
+def num_threads() -> int:
+    return int(lib().oracle_num_threads())
+
+
+def dft1d(x: np.ndarray, sign: int) -> np.ndarray:
+    """Direct O(n^2) DFT: y[k] = sum_j x[j] exp(sign 2 pi i j k / n)."""
+    x = np.ascontiguousarray(x, dtype=np.complex128)
+    y = np.empty_like(x)
+    lib().oracle_dft1d(x.size, sign, _ptr(x), 1, _ptr(y))
+    return y
+
+
+def fft1d(x: np.ndarray, sign: int) -> np.ndarray:
+    """Mixed-radix FFT with the same definition as dft1d."""
+    x = np.ascontiguousarray(x, dtype=np.complex128)
+    y = np.empty_like(x)
+    lib().oracle_fft1d(x.size, sign, _ptr(x), 1, _ptr(y))
+    return y
+
+
+def fft3d(g: np.ndarray, sign: int) -> np.ndarray:
+    """3-D transform (unnormalised) of a [n1][n2][n3] array; +1 inverse, -1 forward."""
+    out = np.ascontiguousarray(g, dtype=np.complex128).copy()
+    nn = np.array(out.shape, dtype=np.int32)
+    lib().oracle_fft3d(_ptr(nn), sign, _ptr(out))
+    return out
+
+
+def apply_h(prob, psi: np.ndarray, nb: int | None = None, terms: int = 7, vloc=None, dmat=None) -> np.ndarray:
+    """y = H psi on a packed psi (per k a [nb][npw_k] block). terms: 1 kin, 2 local, 4 nonlocal."""
+    nb = prob.nb if nb is None else nb
+    b = _Bound(prob, vloc, dmat)
+    x = np.ascontiguousarray(psi, dtype=np.complex128)
+    assert x.size == nb * int(np.sum(prob.npw))
+    y = np.empty_like(x)
+    lib().oracle_apply_h(C.byref(b.s), nb, _ptr(x), _ptr(y), terms)
+    return y
+
+
+def kinetic(prob, k: int) -> np.ndarray:
+    b = _Bound(prob)
+    out = np.empty(int(prob.npw[k]))
+    lib().oracle_kinetic(C.byref(b.s), k, _ptr(out))
+    return out
+
+
+def dense_h(prob, k: int, direct: bool = False) -> np.ndarray:
+    """Explicit H matrix at k-point k (no transform of psi); direct=True also avoids the FFT for V."""
+    b = _Bound(prob)
+    n = int(prob.npw[k])
+    h = np.empty((n, n), dtype=np.complex128)
+    lib().oracle_dense_h(C.byref(b.s), k, 1 if direct else 0, _ptr(h))
+    return h
+
+
+def apply_h_backward(prob, psi, dy, nb=None, vloc=None, dmat=None, want=("psi", "v", "d")):
+    """Adjoint of y = H psi: returns (grad_psi, grad_v, grad_d), None where not requested."""
+    nb = prob.nb if nb is None else nb
+    b = _Bound(prob, vloc, dmat)
+    x = np.ascontiguousarray(psi, dtype=np.complex128)
+    g = np.ascontiguousarray(dy, dtype=np.complex128)
+    gp = np.empty_like(x) if "psi" in want else None
+    gv = np.empty(tuple(prob.fft)) if "v" in want else None
+    gd = np.empty(np.asarray(prob.dmat).size) if "d" in want else None
+    lib().oracle_apply_h_backward(C.byref(b.s), nb, _ptr(x), _ptr(g), _ptr(gp), _ptr(gv), _ptr(gd))
+    return gp, gv, gd
+
+
+# --------------------------------------------------------------------------
+# Block Davidson (Sec. III.B names Davidson as the default eigensolver but
+# gives no steps; this is the block scheme the library implements, with the
+# Teter-Payne-Allan preconditioner that the paper cites for its CG solver).
+# --------------------------------------------------------------------------
+
+def tpa_preconditioner(kin: np.ndarray, ekin: np.ndarray) -> np.ndarray:
+    """K(x) = (27+18x+12x^2+8x^3)/(27+18x+12x^2+8x^3+16x^4), x = |k+G|^2 / max(E_kin, 1e-3)."""
+    x = kin[None, :] / np.maximum(ekin, 1e-3)[:, None]
+    num = 27.0 + 18.0 * x + 12.0 * x * x + 8.0 * x ** 3
+    return num / (num + 16.0 * x ** 4)
+
+
+def _gram(a, b):
+    """M[i, j] = <a_i | b_j> for row-stacked vectors."""
+    return a.conj() @ b.T
+
+
+def cholqr(x: np.ndarray) -> np.ndarray:
+    """One Cholesky-QR pass on the rows of x; shifted Cholesky-QR if S is not positive definite."""
+    s = _gram(x, x)
+    s = 0.5 * (s + s.conj().T)
+    try:
+        l = np.linalg.cholesky(s.T)
+    except np.linalg.LinAlgError:
+        m, n = x.shape
+        shift = 11.0 * (m * n + m * (m + 1)) * np.finfo(float).eps * np.trace(s).real
+        l = np.linalg.cholesky(s.T + shift * np.eye(m))
+    import scipy.linalg as sla
+    return sla.solve_triangular(l, x, lower=True)
+
+
+def davidson_k(hop, psi0: np.ndarray, kin: np.ndarray, tol: float, max_iter: int, ndim: int = 2,
+               drop: float = 1e-10):
+    """Lowest nb eigenpairs of the Hermitian operator hop (rows in, rows out).
+
+    1. Cholesky-QR psi0; W = H psi; Rayleigh-Ritz.
+    2. Repeat: residuals R = W - psi Lambda and their 2-norms; stop when all < tol.
+       Preconditioned corrections T = K (.) R for unconverged bands, projected
+       out of the basis twice (classical Gram-Schmidt, twice), columns whose
+       norm fell below ``drop`` of their pre-projection norm are dropped,
+       Cholesky-QR twice; append T and HT; Rayleigh-Ritz on the whole basis
+       and keep the lowest nb. When the basis would exceed ndim*nb it is
+       restarted to the current Ritz vectors.
+    Returns (eig, psi, resid, iters).
+    """
+    nb = psi0.shape[0]
+    x = cholqr(psi0)
+    w = hop(x)
+    hs = _gram(x, w)
+    hs = 0.5 * (hs + hs.conj().T)
+    lam, y = np.linalg.eigh(hs)
+    x = y.T @ x
+    w = y.T @ w
+    vb, hvb = x.copy(), w.copy()
+    hsub = np.diag(lam).astype(np.complex128)
+    iters = 0
+    while True:
+        r = w - lam[:, None] * x
+        rn = np.sqrt(np.sum(np.abs(r) ** 2, axis=1))
+        if np.all(rn < tol) or iters >= max_iter:
+            break
+        act = np.nonzero(rn >= tol)[0]
+        ekin = np.sum(kin[None, :] * np.abs(x[act]) ** 2, axis=1)
+        t = tpa_preconditioner(kin, ekin) * r[act]
+        if vb.shape[0] + t.shape[0] > ndim * nb:
+            vb, hvb = x.copy(), w.copy()
+            hsub = np.diag(lam).astype(np.complex128)
+        n0 = np.linalg.norm(t, axis=1)
+        for _ in range(2):
+            t = t - _gram(vb, t).T @ vb
+        keep = np.linalg.norm(t, axis=1) >= drop * n0
+        t = t[keep]
+        if t.shape[0] == 0:
+            break
+        t = cholqr(cholqr(t))
+        ht = hop(t)
+        vb = np.concatenate([vb, t])
+        hvb = np.concatenate([hvb, ht])
+        c = _gram(vb, ht)                      # new columns of V^H H V
+        nold = hsub.shape[0]
+        hn = np.zeros((vb.shape[0], vb.shape[0]), dtype=np.complex128)
+        hn[:nold, :nold] = hsub
+        hn[:, nold:] = c
+        hn[nold:, :nold] = c[:nold].conj().T
+        blk = hn[nold:, nold:]
+        hn[nold:, nold:] = 0.5 * (blk + blk.conj().T)
+        hsub = hn
+        theta, y = np.linalg.eigh(hsub)
+        y = y[:, :nb]
+        lam = theta[:nb]
+        x = y.T @ vb
+        w = y.T @ hvb
+        iters += 1
+    return lam, x, rn, iters
+
+
+def davidson(prob, psi0=None, tol=1e-8, max_iter=100, ndim=2, nb=None):
+    """Oracle block Davidson over every k-point; returns (eig [nk][nb], psi packed, resid, iters)."""
+    nb = prob.nb if nb is None else nb
+    psi0 = prob.psi if psi0 is None else psi0
+    off = np.concatenate([[0], np.cumsum(prob.npw)]).astype(np.int64)
+    nk = len(prob.npw)
+    eig = np.empty((nk, nb))
+    res = np.empty((nk, nb))
+    its = np.empty(nk, dtype=np.int64)
+    out = np.empty(nb * int(off[-1]), dtype=np.complex128)
+    for k in range(nk):
+        sub = _single_k(prob, k)
+        npw = int(prob.npw[k])
+        x0 = np.asarray(psi0[nb * off[k]: nb * off[k + 1]]).reshape(nb, npw)
+
+        def hop(rows, sub=sub):
+            return apply_h(sub, rows.reshape(-1), nb=rows.shape[0]).reshape(rows.shape)
+
+        e, x, r, it = davidson_k(hop, x0, kinetic(sub, 0), tol, max_iter, ndim)
+        eig[k], res[k], its[k] = e, r, it
+        out[nb * off[k]: nb * off[k + 1]] = x.reshape(-1)
+    return eig, out, res, its
+
+
+class _SingleK:
+    pass
+
+
+def _single_k(prob, k):
+    """The sub-problem made of k-point k alone (same cell, grid, V, D)."""
+    off = np.concatenate([[0], np.cumsum(prob.npw)]).astype(np.int64)
+    s = _SingleK()
+    s.lattice, s.fft, s.vloc, s.nproj, s.natom = prob.lattice, prob.fft, prob.vloc, prob.nproj, prob.natom
+    s.proj_atom_offset, s.dmat = prob.proj_atom_offset, prob.dmat
+    s.kpts = np.asarray(prob.kpts)[k:k + 1]
+    s.npw = np.asarray(prob.npw)[k:k + 1]
+    s.miller = np.asarray(prob.miller)[off[k]:off[k + 1]]
+    s.beta = np.asarray(prob.beta)[prob.nproj * off[k]: prob.nproj * off[k + 1]]
+    return s
