@@ -1,0 +1,209 @@
+/*
+ * abacus_pw.h -- C ABI of the MI355X (gfx950) plane-wave Hamiltonian library.
+ *
+ * The library applies the Kohn-Sham Hamiltonian of the plane-wave method
+ * (Sec. III.A, the KS equation written in the plane-wave basis) to blocks of
+ * bands, and solves for its lowest eigenpairs with a block Davidson method
+ * (Sec. III.B names Davidson as the iterative eigensolver). The potential is
+ * the norm-conserving split of Sec. II.A ("Pseudopotentials"): a local part
+ * sampled on the real-space FFT grid plus the Kleinman-Bylander separable
+ * nonlocal part sum_ij |beta_i> D_ij <beta_j|.
+ *
+ * Units: Rydberg atomic units. Energies in Ry, lengths in bohr; the kinetic
+ * operator is |k+G|^2 (the paper's Hartree form is (1/2)|k+G|^2).
+ *
+ * Conventions used by every entry point:
+ *   - A k-point's basis is its G-sphere S_k = {G = sum_i m_i b_i : |k+G|^2 < ecutwfc},
+ *     given by the caller as Miller triples (m1, m2, m3) in any order; that
+ *     order is the order of every coefficient array.
+ *   - Real-space grid r_j = sum_i (j_i / N_i) a_i, stored C-ordered [N1][N2][N3]
+ *     (j3 fastest). A Miller index m maps to grid index m mod N_i.
+ *   - psi(r_j) = sum_G psi(G) e^{+iG.r_j} (unnormalised) and
+ *     (V psi)(G) = (1/N) sum_j e^{-iG.r_j} V(r_j) psi(r_j), N = N1 N2 N3; the
+ *     1/N is the grid form of the density transform rho(G) = (1/Omega) int
+ *     rho(r) e^{-iG.r} dr of Sec. III.A.
+ *   - So (H psi)(G) = |k+G|^2 psi(G) + sum_{G'} Vt((m-m') mod N) psi(G')
+ *                     + sum_ij beta_i(G) D_ij <beta_j|psi>,
+ *     with Vt(q) = (1/N) sum_j V(r_j) e^{-2 pi i q.j/N}. Differences G-G'
+ *     wrap modulo the grid, as on any finite FFT grid.
+ *   - Inner products are coefficient sums <x|y> = sum_G conj(x(G)) y(G);
+ *     "orthonormal" means Psi^H Psi = I in that product.
+ *   - Complex arrays are interleaved (re, im): complex128 = two doubles,
+ *     complex64 = two floats, the layout of torch.complex128 / complex64.
+ *   - Band arrays (psi, H psi, gradients) are packed k-major: for each k a
+ *     [nb][npw_k] block, blocks back to back.
+ *
+ * Memory and streams: the caller owns every buffer it passes and the library
+ * never frees caller memory. Device pointers must be device memory of the
+ * current HIP device. `stream` is a hipStream_t (NULL = the null stream); all
+ * device work is enqueued on it. The library keeps a per-process plan cache
+ * (geometry tables, work space) keyed by the problem's geometry; the first call
+ * for a geometry builds the plan (it allocates and synchronises), later calls
+ * only enqueue kernels.
+ *
+ * Errors: every entry point returns 0 on success and a negative ABACUS_PW_E*
+ * code on failure (nothing has been enqueued when a validation error is
+ * returned); abacus_pw_last_error() gives a message for the calling thread.
+ * No C++ exception crosses this interface.
+ */
+#ifndef ABACUS_PW_H
+#define ABACUS_PW_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Status codes. */
+#define ABACUS_PW_OK                    0
+#define ABACUS_PW_NOT_CONVERGED         1   /* Davidson hit max_iter; outputs are valid */
+#define ABACUS_PW_ENULL_ARG            -1   /* a required pointer is NULL */
+#define ABACUS_PW_EBAD_SHAPE           -2   /* nk, npw, nb, nproj, natom or offsets inconsistent */
+#define ABACUS_PW_EBAD_FFT_SIZE        -3   /* a grid length is unsupported, or 2 max|m_i| + 1 > N_i */
+#define ABACUS_PW_EBAD_SPHERE          -4   /* duplicate Miller triple, or |k+G|^2 >= ecutwfc */
+#define ABACUS_PW_EBAD_D               -5   /* a D block is not symmetric (1e-14 relative) */
+#define ABACUS_PW_ENONFINITE           -6   /* NaN/Inf in V_loc or D */
+#define ABACUS_PW_EBAD_PRECISION       -7   /* unknown precision value, or mode not offered by this entry point */
+#define ABACUS_PW_EHIP                 -8   /* a HIP runtime call failed */
+#define ABACUS_PW_ECHOLESKY            -9   /* Davidson: Gram matrix not positive definite even after a shift */
+#define ABACUS_PW_EINTERNAL           -10
+
+/* Arithmetic modes (the `precision` argument). */
+#define ABACUS_PW_FP64        0  /* complex128 psi; FP64 FFTs and GEMMs */
+#define ABACUS_PW_FP32        1  /* complex64 psi; FP32 FFTs and FP32-MFMA GEMMs with FP32 accumulation */
+#define ABACUS_PW_MIXED_BF16  2  /* complex128 psi in and out; FP32 FFTs; BF16 GEMM operands, FP32 accumulation */
+#define ABACUS_PW_MIXED_FP32  3  /* complex128 psi in and out; FP32 FFTs; FP32 GEMM operands, FP32 accumulation */
+
+/* problem.flags */
+#define ABACUS_PW_STATIC_OPERATOR 1u  /* V_loc, beta and D contents are unchanged since the last call
+                                         with the same pointers: reduced-precision copies may be reused */
+
+/*
+ * The problem statement (the plane-wave KS problem of Sec. III.A with the
+ * pseudopotential split of Sec. II.A).
+ *
+ * lattice          host, rows a1, a2, a3 (bohr).
+ * fft              N1, N2, N3: grid lengths; each must be a product of 2, 3 and 5
+ *                  that the library has a transform for (see abacus_pw_fft_supported).
+ * ecutwfc          kinetic cutoff (Ry); every sphere point must satisfy |k+G|^2 < ecutwfc.
+ * nk, kpts         host [nk][3] cartesian k-points (bohr^-1).
+ * npw              host [nk] sphere sizes.
+ * miller           host [sum npw][3] int32 Miller triples, k-major (the G-sphere index map).
+ *                  Keyed by pointer in the plan cache: after editing it in place call
+ *                  abacus_pw_plan_reset().
+ * vloc             device [N1][N2][N3] float64 local potential V_loc(r_j) (Ry).
+ * nproj            projectors per k-point (same count and order at every k).
+ * natom            number of atom blocks.
+ * proj_atom_offset host [natom+1]: projectors of atom a are [off[a], off[a+1]).
+ * beta             device complex128, per k a [nproj][npw_k] block of beta_i(k+G).
+ * dmat             device float64, per atom a row-major [np_a][np_a] symmetric block of D (Ry),
+ *                  blocks back to back.
+ * flags            ABACUS_PW_STATIC_OPERATOR or 0.
+ *
+ * V_loc and D are checked (finite; D symmetric) when a plan is first built.
+ */
+typedef struct abacus_pw_problem {
+    double lattice[9];
+    int fft[3];
+    double ecutwfc;
+    int nk;
+    const double *kpts;
+    const int *npw;
+    const int *miller;
+    const double *vloc;
+    int nproj;
+    int natom;
+    const int *proj_atom_offset;
+    const void *beta;
+    const double *dmat;
+    unsigned flags;
+} abacus_pw_problem;
+
+/*
+ * hpsi = H psi for nb bands at every k-point (KS equation in the plane-wave
+ * basis, Sec. III.A; local + Kleinman-Bylander terms, Sec. II.A).
+ *
+ * psi   device, packed [k][nb][npw_k]: complex128 for FP64 and MIXED_*, complex64 for FP32.
+ * hpsi  device, same layout and type as psi; overwritten. Must not alias psi.
+ * Asynchronous: returns after enqueueing on `stream` (after the plan exists).
+ * Errors: ENULL_ARG, EBAD_SHAPE, EBAD_FFT_SIZE, EBAD_SPHERE, EBAD_D, ENONFINITE,
+ * EBAD_PRECISION, EHIP.
+ */
+int abacus_pw_apply_h(const abacus_pw_problem *p, int precision, int nb, const void *psi, void *hpsi,
+                      void *stream);
+
+/*
+ * Lowest nb eigenpairs of H at every k-point by block Davidson (Sec. III.B
+ * names Davidson as the eigensolver of the plane-wave code; the steps are the
+ * library's, listed in the design notes): residuals R = H Psi - Psi Lambda,
+ * Teter-Payne-Allan preconditioned corrections for unconverged bands, two
+ * classical Gram-Schmidt passes against the basis, Cholesky-QR, Rayleigh-Ritz
+ * on the basis [Psi, T] (restarted to the Ritz vectors when it would exceed
+ * ndim*nb columns).
+ *
+ * psi_inout device complex128 packed [k][nb][npw_k]: initial guess in, Ritz vectors out
+ *           (orthonormal).
+ * eig       host float64 [nk][nb]: Ritz values, ascending (Ry).
+ * tol       residual tolerance: stop when every ||H psi_n - eps_n psi_n||_2 < tol.
+ * max_iter  maximum number of correction steps per k-point.
+ * ndim      basis size factor (>= 2).
+ * iters     host int [nk] (may be NULL): correction steps taken.
+ * resid     host float64 [nk][nb] (may be NULL): final residual norms, computed in FP64.
+ * precision ABACUS_PW_FP64, or ABACUS_PW_MIXED_FP32 / ABACUS_PW_MIXED_BF16: reduced-precision
+ *           Davidson steps followed by FP64 refinement steps to the same tol.
+ * Returns 0 when every k converged, ABACUS_PW_NOT_CONVERGED (+1) when max_iter was
+ * reached (outputs valid), or a negative code. Synchronises `stream` before returning.
+ */
+int abacus_pw_davidson(const abacus_pw_problem *p, int precision, int nb, void *psi_inout, double *eig,
+                       double tol, int max_iter, int ndim, int *iters, double *resid, void *stream);
+
+/*
+ * Adjoint of hpsi = H psi for a real loss L with upstream gradient
+ * dY = dL/dRe(hpsi) + i dL/dIm(hpsi) (PyTorch's convention for complex tensors):
+ *   grad_psi    = H dY                                   (H is Hermitian)
+ *   grad_vloc(r_j) = (1/N) sum_{k,n} Re( conj(gamma_n(r_j)) psi_n(r_j) ),
+ *                 gamma_n, psi_n the unnormalised inverse transforms of dY_n, psi_n
+ *   grad_dmat[a](i,j) = Re sum_{k,n} Q_in conj(P_jn),  P = B^H psi, Q = B^H dY
+ * psi, dY   device, layout and type as in abacus_pw_apply_h (FP64 or FP32 precision).
+ * grad_psi  device, like psi, overwritten (NULL: skipped).
+ * grad_vloc device float64 [N1][N2][N3], overwritten (NULL: skipped).
+ * grad_dmat device float64, layout of dmat, overwritten, not symmetrised (NULL: skipped).
+ * Reductions over bands and k run in a fixed order (repeatable bit for bit).
+ * Asynchronous. Errors as for abacus_pw_apply_h.
+ */
+int abacus_pw_apply_h_backward(const abacus_pw_problem *p, int precision, int nb, const void *psi,
+                               const void *dY, void *grad_psi, double *grad_vloc, double *grad_dmat,
+                               void *stream);
+
+/* Message for the last error on the calling thread (truncated to size). Returns len. */
+int abacus_pw_last_error(char *buf, int size);
+
+/* 1 when the library has a transform of length n (a product of 2, 3, 5), else 0. */
+int abacus_pw_fft_supported(int n);
+
+/* Drops every cached plan (frees their device work space). Synchronises the device. */
+int abacus_pw_plan_reset(void);
+
+/*
+ * Optional per-kernel timing. When enabled, the library records a pair of HIP
+ * events around every kernel it enqueues, on the stream it enqueues it on, and
+ * accumulates elapsed time per kernel name at the next abacus_pw_profile_read.
+ * abacus_pw_profile_read synchronises, then writes up to max_entries records
+ * "name\tlaunches\ttotal_ms\n" into buf (NUL-terminated); returns the number of
+ * records, or a negative code.
+ */
+int abacus_pw_profile_enable(int on);
+int abacus_pw_profile_read(char *buf, int size);
+
+/*
+ * Tuning knobs (the autotuner sets these; 0 = library default).
+ * band_batch: bands per FFT batch; splitk_chunk: K-chunk of the projection GEMM.
+ */
+int abacus_pw_set_tuning(int band_batch, int splitk_chunk);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* ABACUS_PW_H */

@@ -1,0 +1,204 @@
+"""ctypes binding of libabacus_pw.so (include/abacus_pw.h).
+
+Argument marshalling only: every step of H psi, its adjoint and Davidson runs
+in the library's HIP kernels. torch supplies device memory and the stream.
+The library must be built (``python -m paper_2501_08697_amd.build``); when it
+is missing every call raises instead of falling back to anything else.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libabacus_pw.so")
+
+FP64, FP32, MIXED_BF16, MIXED_FP32 = 0, 1, 2, 3
+STATIC_OPERATOR = 1
+
+ERRORS = {
+    -1: "ENULL_ARG", -2: "EBAD_SHAPE", -3: "EBAD_FFT_SIZE", -4: "EBAD_SPHERE", -5: "EBAD_D",
+    -6: "ENONFINITE", -7: "EBAD_PRECISION", -8: "EHIP", -9: "ECHOLESKY", -10: "EINTERNAL",
+}
+
+EXPORTS = ["abacus_pw_apply_h", "abacus_pw_davidson", "abacus_pw_apply_h_backward", "abacus_pw_last_error",
+           "abacus_pw_fft_supported", "abacus_pw_plan_reset", "abacus_pw_profile_enable",
+           "abacus_pw_profile_read", "abacus_pw_set_tuning"]
+
+
+class AbacusPwError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{ERRORS.get(code, code)}: {msg}")
+        self.code = code
+        self.name = ERRORS.get(code, str(code))
+
+
+class CProblem(C.Structure):
+    _fields_ = [
+        ("lattice", C.c_double * 9), ("fft", C.c_int * 3), ("ecutwfc", C.c_double), ("nk", C.c_int),
+        ("kpts", C.c_void_p), ("npw", C.c_void_p), ("miller", C.c_void_p), ("vloc", C.c_void_p),
+        ("nproj", C.c_int), ("natom", C.c_int), ("proj_atom_offset", C.c_void_p), ("beta", C.c_void_p),
+        ("dmat", C.c_void_p), ("flags", C.c_uint),
+    ]
+
+
+_lib = None
+
+
+def lib():
+    """Loads the HIP library (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with python -m paper_2501_08697_amd.build")
+        L = C.CDLL(LIB_PATH)
+        P, vp, i, d = C.POINTER(CProblem), C.c_void_p, C.c_int, C.c_double
+        L.abacus_pw_apply_h.argtypes = [P, i, i, vp, vp, vp]
+        L.abacus_pw_apply_h_backward.argtypes = [P, i, i, vp, vp, vp, vp, vp, vp]
+        L.abacus_pw_davidson.argtypes = [P, i, i, vp, vp, d, i, i, vp, vp, vp]
+        L.abacus_pw_last_error.argtypes = [C.c_char_p, i]
+        L.abacus_pw_fft_supported.argtypes = [i]
+        L.abacus_pw_profile_enable.argtypes = [i]
+        L.abacus_pw_profile_read.argtypes = [C.c_char_p, i]
+        L.abacus_pw_set_tuning.argtypes = [i, i]
+        _lib = L
+    return _lib
+
+
+def last_error() -> str:
+    buf = C.create_string_buffer(1024)
+    lib().abacus_pw_last_error(buf, 1024)
+    return buf.value.decode()
+
+
+def check(code: int) -> int:
+    if code < 0:
+        raise AbacusPwError(code, last_error())
+    return code
+
+
+def _stream(stream=None) -> int:
+    import torch
+    s = torch.cuda.current_stream() if stream is None else stream
+    return int(s.cuda_stream)
+
+
+class DeviceProblem:
+    """A problem with its operator arrays in device memory, ready for the C ABI.
+
+    Host arrays (lattice, kpts, npw, miller, proj_atom_offset) are kept as
+    contiguous numpy buffers; vloc, beta and dmat as torch device tensors.
+    """
+
+    def __init__(self, prob, device="cuda", vloc=None, dmat=None, beta=None, static=True):
+        import torch
+        self.prob = prob
+        self.nk = int(len(prob.npw))
+        self.fft = tuple(int(x) for x in prob.fft)
+        self.npw = np.ascontiguousarray(prob.npw, dtype=np.int32)
+        self.pw_off = np.concatenate([[0], np.cumsum(self.npw)]).astype(np.int64)
+        self._kpts = np.ascontiguousarray(prob.kpts, dtype=np.float64)
+        self._miller = np.ascontiguousarray(prob.miller, dtype=np.int32)
+        self._offs = np.ascontiguousarray(prob.proj_atom_offset, dtype=np.int32)
+        self.vloc = vloc if vloc is not None else torch.from_numpy(np.ascontiguousarray(prob.vloc)).to(device)
+        self.beta = beta if beta is not None else torch.from_numpy(np.ascontiguousarray(prob.beta)).to(device)
+        self.dmat = dmat if dmat is not None else torch.from_numpy(np.ascontiguousarray(prob.dmat)).to(device)
+        self.nproj, self.natom = int(prob.nproj), int(prob.natom)
+        self.static = static
+
+    def c(self, vloc=None, dmat=None) -> CProblem:
+        s = CProblem()
+        s.lattice[:] = [float(x) for x in np.asarray(self.prob.lattice, dtype=np.float64).reshape(-1)]
+        s.fft[:] = list(self.fft)
+        s.ecutwfc = float(self.prob.ecut)
+        s.nk = self.nk
+        s.kpts = self._kpts.ctypes.data
+        s.npw = self.npw.ctypes.data
+        s.miller = self._miller.ctypes.data
+        v = self.vloc if vloc is None else vloc
+        dm = self.dmat if dmat is None else dmat
+        s.vloc = v.data_ptr()
+        s.nproj, s.natom = self.nproj, self.natom
+        s.proj_atom_offset = self._offs.ctypes.data if self.nproj > 0 else None
+        s.beta = self.beta.data_ptr() if self.nproj > 0 else None
+        s.dmat = dm.data_ptr() if self.nproj > 0 else None
+        s.flags = STATIC_OPERATOR if (self.static and vloc is None and dmat is None) else 0
+        return s
+
+    def psi_len(self, nb: int) -> int:
+        return nb * int(self.pw_off[-1])
+
+
+def apply_h(dp: DeviceProblem, psi, precision: int = FP64, nb: int | None = None, out=None, stream=None,
+            vloc=None, dmat=None):
+    """H psi for a packed psi tensor (complex128, or complex64 for FP32)."""
+    import torch
+    nb = dp.prob.nb if nb is None else nb
+    if psi.numel() != dp.psi_len(nb):
+        raise ValueError("psi has the wrong length for nb bands")
+    psi = psi.contiguous()
+    y = torch.empty_like(psi) if out is None else out
+    cp = dp.c(vloc, dmat)
+    check(lib().abacus_pw_apply_h(C.byref(cp), int(precision), int(nb), psi.data_ptr(), y.data_ptr(),
+                                  _stream(stream)))
+    return y
+
+
+def apply_h_backward(dp: DeviceProblem, psi, dy, precision: int = FP64, nb: int | None = None, want=("psi", "v", "d"),
+                     stream=None, vloc=None, dmat=None):
+    """(grad_psi, grad_vloc, grad_dmat) of L with upstream dy = dL/d(H psi)."""
+    import torch
+    nb = dp.prob.nb if nb is None else nb
+    psi, dy = psi.contiguous(), dy.contiguous()
+    gp = torch.empty_like(psi) if "psi" in want else None
+    gv = torch.empty(dp.fft, dtype=torch.float64, device=psi.device) if "v" in want else None
+    gd = torch.empty_like(dp.dmat) if "d" in want else None
+    cp = dp.c(vloc, dmat)
+    check(lib().abacus_pw_apply_h_backward(C.byref(cp), int(precision), int(nb), psi.data_ptr(), dy.data_ptr(),
+                                           None if gp is None else gp.data_ptr(),
+                                           None if gv is None else gv.data_ptr(),
+                                           None if gd is None else gd.data_ptr(), _stream(stream)))
+    return gp, gv, gd
+
+
+def davidson(dp: DeviceProblem, psi, tol=1e-8, max_iter=100, ndim=2, precision: int = FP64, nb: int | None = None,
+             stream=None):
+    """Block Davidson; psi (complex128) is updated in place. Returns (eig, resid, iters, status)."""
+    nb = dp.prob.nb if nb is None else nb
+    eig = np.zeros((dp.nk, nb))
+    res = np.zeros((dp.nk, nb))
+    its = np.zeros(dp.nk, dtype=np.int32)
+    cp = dp.c()
+    st = check(lib().abacus_pw_davidson(C.byref(cp), int(precision), int(nb), psi.data_ptr(), eig.ctypes.data,
+                                        float(tol), int(max_iter), int(ndim), its.ctypes.data, res.ctypes.data,
+                                        _stream(stream)))
+    return eig, res, its, st
+
+
+def fft_supported(n: int) -> bool:
+    return bool(lib().abacus_pw_fft_supported(int(n)))
+
+
+def plan_reset():
+    check(lib().abacus_pw_plan_reset())
+
+
+def set_tuning(band_batch: int = 0, splitk_chunk: int = 0):
+    check(lib().abacus_pw_set_tuning(int(band_batch), int(splitk_chunk)))
+
+
+def profile_enable(on: bool = True):
+    check(lib().abacus_pw_profile_enable(1 if on else 0))
+
+
+def profile_read() -> dict:
+    """{kernel name: (launches, total_ms)} accumulated since the last read."""
+    buf = C.create_string_buffer(1 << 16)
+    check(lib().abacus_pw_profile_read(buf, 1 << 16))
+    out = {}
+    for line in buf.value.decode().splitlines():
+        name, n, ms = line.split("\t")
+        out[name] = (int(n), float(ms))
+    return out

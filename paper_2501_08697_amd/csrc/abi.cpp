@@ -1,0 +1,194 @@
+// C entry points, error messages and per-kernel timing.
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "abacus_pw.h"
+#include "common.hpp"
+#include "hamiltonian.hpp"
+#include "local.hpp"
+#include "plan.hpp"
+
+namespace apw {
+
+// ------------------------------------------------------------------ errors --
+static thread_local std::string t_err;
+
+int set_error(int code, const std::string &msg) {
+    t_err = msg;
+    return code;
+}
+
+// ----------------------------------------------------------------- timing --
+bool g_prof_on = false;
+namespace {
+struct Pending {
+    const char *name;
+    hipEvent_t a, b;
+};
+std::mutex g_prof_mu;
+std::vector<Pending> g_pending;
+std::vector<hipEvent_t> g_pool;
+thread_local std::vector<std::pair<const char *, hipEvent_t>> t_open;
+std::map<std::string, std::pair<long, double>> g_totals;
+
+hipEvent_t take_event() {
+    std::lock_guard<std::mutex> l(g_prof_mu);
+    if (!g_pool.empty()) {
+        hipEvent_t e = g_pool.back();
+        g_pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    (void)hipEventCreate(&e);
+    return e;
+}
+}  // namespace
+
+void prof_begin(const char *name, hipStream_t s) {
+    hipEvent_t e = take_event();
+    (void)hipEventRecord(e, s);
+    t_open.emplace_back(name, e);
+}
+
+void prof_end(hipStream_t s) {
+    if (t_open.empty()) return;
+    auto [name, a] = t_open.back();
+    t_open.pop_back();
+    hipEvent_t b = take_event();
+    (void)hipEventRecord(b, s);
+    std::lock_guard<std::mutex> l(g_prof_mu);
+    g_pending.push_back(Pending{name, a, b});
+}
+
+static int prof_collect() {
+    std::vector<Pending> todo;
+    {
+        std::lock_guard<std::mutex> l(g_prof_mu);
+        todo.swap(g_pending);
+    }
+    for (auto &p : todo) {
+        APW_HIP(hipEventSynchronize(p.b));
+        float ms = 0.f;
+        APW_HIP(hipEventElapsedTime(&ms, p.a, p.b));
+        std::lock_guard<std::mutex> l(g_prof_mu);
+        auto &t = g_totals[p.name];
+        t.first += 1;
+        t.second += ms;
+        g_pool.push_back(p.a);
+        g_pool.push_back(p.b);
+    }
+    return ABACUS_PW_OK;
+}
+
+int plan_reset_all();
+
+}  // namespace apw
+
+using namespace apw;
+
+template <typename F> static int guarded(F &&f) {
+    try {
+        return f();
+    } catch (const std::exception &e) {
+        return set_error(ABACUS_PW_EINTERNAL, std::string("internal error: ") + e.what());
+    } catch (...) {
+        return set_error(ABACUS_PW_EINTERNAL, "internal error");
+    }
+}
+
+extern "C" {
+
+int abacus_pw_last_error(char *buf, int size) {
+    if (!buf || size <= 0) return (int)t_err.size();
+    std::snprintf(buf, (size_t)size, "%s", t_err.c_str());
+    return (int)t_err.size();
+}
+
+int abacus_pw_fft_supported(int n) { return local_length_supported(n); }
+
+int abacus_pw_plan_reset(void) {
+    return guarded([&] { return plan_reset_all(); });
+}
+
+int abacus_pw_set_tuning(int band_batch, int splitk_chunk) {
+    if (band_batch < 0 || splitk_chunk < 0) return set_error(ABACUS_PW_EBAD_SHAPE, "negative tuning value");
+    g_band_batch = band_batch;
+    g_splitk_chunk = splitk_chunk;
+    return ABACUS_PW_OK;
+}
+
+int abacus_pw_profile_enable(int on) {
+    g_prof_on = on != 0;
+    return ABACUS_PW_OK;
+}
+
+int abacus_pw_profile_read(char *buf, int size) {
+    return guarded([&]() -> int {
+        APW_HIP(hipDeviceSynchronize());
+        APW_TRY(prof_collect());
+        std::string out;
+        int n = 0;
+        {
+            std::lock_guard<std::mutex> l(g_prof_mu);
+            for (auto &kv : g_totals) {
+                char line[256];
+                std::snprintf(line, sizeof line, "%s\t%ld\t%.6f\n", kv.first.c_str(), kv.second.first,
+                              kv.second.second);
+                out += line;
+                ++n;
+            }
+            g_totals.clear();
+        }
+        if (buf && size > 0) std::snprintf(buf, (size_t)size, "%s", out.c_str());
+        return n;
+    });
+}
+
+int abacus_pw_apply_h(const abacus_pw_problem *p, int precision, int nb, const void *psi, void *hpsi, void *stream) {
+    return guarded([&]() -> int {
+        if (!psi || !hpsi) return set_error(ABACUS_PW_ENULL_ARG, "psi and hpsi are required");
+        if (psi == hpsi) return set_error(ABACUS_PW_EBAD_SHAPE, "hpsi must not alias psi");
+        if (nb < 1) return set_error(ABACUS_PW_EBAD_SHAPE, "nb must be >= 1");
+        if (precision < 0 || precision > 3) return set_error(ABACUS_PW_EBAD_PRECISION, "unknown precision");
+        Plan *P = nullptr;
+        APW_TRY(get_plan(p, &P));
+        return apply_h_all(*p, *P, precision, nb, psi, hpsi, static_cast<hipStream_t>(stream));
+    });
+}
+
+int abacus_pw_apply_h_backward(const abacus_pw_problem *p, int precision, int nb, const void *psi, const void *dY,
+                               void *grad_psi, double *grad_vloc, double *grad_dmat, void *stream) {
+    return guarded([&]() -> int {
+        if (!psi || !dY) return set_error(ABACUS_PW_ENULL_ARG, "psi and dY are required");
+        if (nb < 1) return set_error(ABACUS_PW_EBAD_SHAPE, "nb must be >= 1");
+        if (precision != ABACUS_PW_FP64 && precision != ABACUS_PW_FP32)
+            return set_error(ABACUS_PW_EBAD_PRECISION, "the adjoint runs in FP64 or FP32");
+        Plan *P = nullptr;
+        APW_TRY(get_plan(p, &P));
+        return apply_h_backward_all(*p, *P, precision, nb, psi, dY, grad_psi, grad_vloc, grad_dmat,
+                                    static_cast<hipStream_t>(stream));
+    });
+}
+
+int abacus_pw_davidson(const abacus_pw_problem *p, int precision, int nb, void *psi_inout, double *eig, double tol,
+                       int max_iter, int ndim, int *iters, double *resid, void *stream) {
+    return guarded([&]() -> int {
+        if (!psi_inout || !eig) return set_error(ABACUS_PW_ENULL_ARG, "psi_inout and eig are required");
+        if (nb < 1 || max_iter < 0 || ndim < 2) return set_error(ABACUS_PW_EBAD_SHAPE, "need nb >= 1, max_iter >= 0, ndim >= 2");
+        if (!(tol > 0.0)) return set_error(ABACUS_PW_EBAD_SHAPE, "tol must be > 0");
+        if (precision != ABACUS_PW_FP64 && precision != ABACUS_PW_MIXED_FP32 && precision != ABACUS_PW_MIXED_BF16)
+            return set_error(ABACUS_PW_EBAD_PRECISION, "Davidson runs in FP64 or a MIXED mode");
+        Plan *P = nullptr;
+        APW_TRY(get_plan(p, &P));
+        for (int k = 0; k < p->nk; ++k)
+            if (p->npw[k] < nb) return set_error(ABACUS_PW_EBAD_SHAPE, "nb exceeds the sphere size");
+        return davidson_all(*p, *P, precision, nb, psi_inout, eig, tol, max_iter, ndim, iters, resid,
+                            static_cast<hipStream_t>(stream));
+    });
+}
+
+}  // extern "C"

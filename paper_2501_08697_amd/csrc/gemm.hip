@@ -1,0 +1,344 @@
+// Complex GEMMs on the matrix cores (MFMA) for the Kleinman-Bylander term
+// sum_ij |beta_i> D_ij <beta_j| psi (Sec. II.A) and for the Davidson subspace
+// products. Two shapes cover every use, both with K-contiguous row vectors:
+//
+//   CN  C[j][i] = alpha * sum_k conj(A[i][k]) B[j][k] + beta * C[j][i]
+//       (projections <a_i|b_j>; K = npw is long, so K is split across
+//        work-groups and the partial tiles are summed in a fixed order)
+//   NN  C[j][g] = alpha * sum_i A[j][i] B[i][g] + beta * C[j][g]
+//       (combinations of basis vectors: Y += B Q, Psi = V Y)
+//
+// Tiles: a 256-thread work-group owns a 64 x 64 output tile; each of its four
+// waves a 32 x 32 quarter as 2 x 2 blocks of 16 x 16 MFMA results, one block
+// for the real and one for the imaginary part. Operands are staged in LDS
+// (16 k per stage). FP64 uses v_mfma_f64_16x16x4f64, FP32 v_mfma_f32_16x16x4f32;
+// both take one value of A and of B per lane (A[i][k] at lane i + 16 k, B[k][j]
+// at lane j + 16 k) and return four values per lane in column j = lane % 16.
+// The row of element e differs: the FP64 instruction interleaves rows
+// (i = lane / 16 + 4 e), the FP32 one blocks them (i = 4 (lane / 16) + e);
+// Acc<T>::row encodes this (measured on gfx950).
+#include "common.hpp"
+#include "gemm.hpp"
+
+namespace apw {
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+typedef float f4 __attribute__((ext_vector_type(4)));
+
+template <typename T> struct Acc;
+template <> struct Acc<double> {
+    using V = d4;
+    __device__ static V zero() { return V{0.0, 0.0, 0.0, 0.0}; }
+    __device__ static V mma(double a, double b, V c) { return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0); }
+    __device__ static int row(int lane, int e) { return (lane >> 4) + 4 * e; }
+};
+template <> struct Acc<float> {
+    using V = f4;
+    __device__ static V zero() { return V{0.f, 0.f, 0.f, 0.f}; }
+    __device__ static V mma(float a, float b, V c) { return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0); }
+    __device__ static int row(int lane, int e) { return 4 * (lane >> 4) + e; }
+};
+
+constexpr int TM = 64, TN = 64, KT = 16, KP = KT + 1;
+
+// ----------------------------------------------------------------- CN ------
+// part[s][j][i] = sum over k in split s of conj(A[i][k]) B[j][k]
+template <typename T>
+__global__ __launch_bounds__(256) void k_gemm_cn_part(int M, int N, int K, int kchunk, const cx<T> *__restrict__ A,
+                                                      int64_t lda, const cx<T> *__restrict__ B, int64_t ldb,
+                                                      cx<T> *__restrict__ part) {
+    __shared__ cx<T> As[TM][KP];
+    __shared__ cx<T> Bs[TN][KP];
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int i0 = blockIdx.x * TM, j0 = blockIdx.y * TN, s = blockIdx.z;
+    const int kb = s * kchunk, ke = min(K, kb + kchunk);
+    using AV = typename Acc<T>::V;
+    AV cre[2][2], cim[2][2];
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) cre[a][b] = cim[a][b] = Acc<T>::zero();
+    const int lr = tid >> 2, lk = (tid & 3) * 4;   // loader: row, first k of 4
+    const int wi = (w & 1) * 32, wj = (w >> 1) * 32;
+    for (int k0 = kb; k0 < ke; k0 += KT) {
+        {
+            const int gi = i0 + lr, gj = j0 + lr;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int gk = k0 + lk + q;
+                As[lr][lk + q] = (gi < M && gk < ke) ? A[gi * lda + gk] : cx<T>{T(0), T(0)};
+                Bs[lr][lk + q] = (gj < N && gk < ke) ? B[gj * ldb + gk] : cx<T>{T(0), T(0)};
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int kk = 4 * q + (lane >> 4);
+            cx<T> a[2], b[2];
+#pragma unroll
+            for (int r = 0; r < 2; ++r) a[r] = As[wi + 16 * r + (lane & 15)][kk];
+#pragma unroll
+            for (int c = 0; c < 2; ++c) b[c] = Bs[wj + 16 * c + (lane & 15)][kk];
+#pragma unroll
+            for (int r = 0; r < 2; ++r)
+#pragma unroll
+                for (int c = 0; c < 2; ++c) {
+                    // conj(a) b = (ar br + ai bi) + i (ar bi - ai br)
+                    cre[r][c] = Acc<T>::mma(a[r].re, b[c].re, cre[r][c]);
+                    cre[r][c] = Acc<T>::mma(a[r].im, b[c].im, cre[r][c]);
+                    cim[r][c] = Acc<T>::mma(a[r].re, b[c].im, cim[r][c]);
+                    cim[r][c] = Acc<T>::mma(-a[r].im, b[c].re, cim[r][c]);
+                }
+        }
+        __syncthreads();
+    }
+    cx<T> *out = part + (int64_t)s * N * M;
+#pragma unroll
+    for (int r = 0; r < 2; ++r)
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+            const int gj = j0 + wj + 16 * c + (lane & 15);
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int gi = i0 + wi + 16 * r + Acc<T>::row(lane, e);
+                if (gi < M && gj < N) out[(int64_t)gj * M + gi] = cx<T>{cre[r][c][e], cim[r][c][e]};
+            }
+        }
+}
+
+// C[j][i] = alpha * sum_s part[s][j][i] + beta * C[j][i]   (fixed summation order)
+template <typename T>
+__global__ void k_reduce(int M, int N, int nsplit, const cx<T> *__restrict__ part, cx<T> *__restrict__ C, int64_t ldc,
+                         double alpha, double beta) {
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= (int64_t)M * N) return;
+    const int j = (int)(idx / M), i = (int)(idx - (int64_t)j * M);
+    double re = 0.0, im = 0.0;
+    for (int s = 0; s < nsplit; ++s) {
+        const cx<T> v = part[(int64_t)s * M * N + idx];
+        re += (double)v.re;
+        im += (double)v.im;
+    }
+    cx<T> *c = C + (int64_t)j * ldc + i;
+    if (beta != 0.0) {
+        re = alpha * re + beta * (double)c->re;
+        im = alpha * im + beta * (double)c->im;
+    } else {
+        re *= alpha;
+        im *= alpha;
+    }
+    *c = cx<T>{(T)re, (T)im};
+}
+
+// P[j][i] = sum_s part[s][j][i]; Q[j][i] = sum_t D_blk(i)[i - lo][t] P[j][lo + t]
+// One work-group per band j; P of the band is staged in LDS.
+template <typename T>
+__global__ __launch_bounds__(256) void k_reduce_dapply(int M, int nsplit, const cx<T> *__restrict__ part, int N,
+                                                       const double *__restrict__ dmat, const int *__restrict__ blo,
+                                                       const int *__restrict__ bn, const int *__restrict__ bdoff,
+                                                       cx<T> *__restrict__ P, cx<T> *__restrict__ Q) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    cx<double> *pl = reinterpret_cast<cx<double> *>(smem);
+    const int j = blockIdx.x;
+    for (int i = threadIdx.x; i < M; i += blockDim.x) {
+        double re = 0.0, im = 0.0;
+        for (int s = 0; s < nsplit; ++s) {
+            const cx<T> v = part[((int64_t)s * N + j) * M + i];
+            re += (double)v.re;
+            im += (double)v.im;
+        }
+        pl[i] = cx<double>{re, im};
+        if (P) P[(int64_t)j * M + i] = cx<T>{(T)re, (T)im};
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < M; i += blockDim.x) {
+        const int lo = blo[i], n = bn[i];
+        const double *d = dmat + bdoff[i] + (int64_t)(i - lo) * n;
+        double re = 0.0, im = 0.0;
+        for (int t = 0; t < n; ++t) {
+            re += d[t] * pl[lo + t].re;
+            im += d[t] * pl[lo + t].im;
+        }
+        Q[(int64_t)j * M + i] = cx<T>{(T)re, (T)im};
+    }
+}
+
+// ----------------------------------------------------------------- NN ------
+// C[j][g] = alpha * sum_i A[j][i] B[i][g] + beta * C[j][g]
+template <typename T, typename TC>
+__global__ __launch_bounds__(256) void k_gemm_nn(int M, int G, int K, const cx<T> *__restrict__ A, int64_t lda,
+                                                 const cx<T> *__restrict__ B, int64_t ldb, cx<TC> *__restrict__ C,
+                                                 int64_t ldc, double alpha, double beta) {
+    __shared__ cx<T> As[TM][KP];
+    __shared__ cx<T> Bs[KT][TN + 1];
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int j0 = blockIdx.y * TM, g0 = blockIdx.x * TN;
+    using AV = typename Acc<T>::V;
+    AV cre[2][2], cim[2][2];
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) cre[a][b] = cim[a][b] = Acc<T>::zero();
+    const int wj = (w & 1) * 32, wg = (w >> 1) * 32;
+    const int ar = tid >> 2, ak = (tid & 3) * 4;       // A loader: row j, 4 consecutive i
+    const int bk = tid >> 4, bg = (tid & 15) * 4;      // B loader: row i, 4 consecutive g
+    for (int k0 = 0; k0 < K; k0 += KT) {
+        {
+            const int gj = j0 + ar;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int gk = k0 + ak + q;
+                As[ar][ak + q] = (gj < M && gk < K) ? A[gj * lda + gk] : cx<T>{T(0), T(0)};
+            }
+            const int gk = k0 + bk;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int gg = g0 + bg + q;
+                Bs[bk][bg + q] = (gk < K && gg < G) ? B[gk * ldb + gg] : cx<T>{T(0), T(0)};
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int kk = 4 * q + (lane >> 4);
+            cx<T> a[2], b[2];
+#pragma unroll
+            for (int r = 0; r < 2; ++r) a[r] = As[wj + 16 * r + (lane & 15)][kk];
+#pragma unroll
+            for (int c = 0; c < 2; ++c) b[c] = Bs[kk][wg + 16 * c + (lane & 15)];
+#pragma unroll
+            for (int r = 0; r < 2; ++r)
+#pragma unroll
+                for (int c = 0; c < 2; ++c) {
+                    // a b = (ar br - ai bi) + i (ar bi + ai br)
+                    cre[r][c] = Acc<T>::mma(a[r].re, b[c].re, cre[r][c]);
+                    cre[r][c] = Acc<T>::mma(-a[r].im, b[c].im, cre[r][c]);
+                    cim[r][c] = Acc<T>::mma(a[r].re, b[c].im, cim[r][c]);
+                    cim[r][c] = Acc<T>::mma(a[r].im, b[c].re, cim[r][c]);
+                }
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int r = 0; r < 2; ++r)
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+            const int gg = g0 + wg + 16 * c + (lane & 15);
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int gj = j0 + wj + 16 * r + Acc<T>::row(lane, e);
+                if (gj < M && gg < G) {
+                    cx<TC> *p = C + (int64_t)gj * ldc + gg;
+                    double re = alpha * (double)cre[r][c][e], im = alpha * (double)cim[r][c][e];
+                    if (beta != 0.0) {
+                        const cx<TC> o = *p;
+                        re += beta * (double)o.re;
+                        im += beta * (double)o.im;
+                    }
+                    *p = cx<TC>{(TC)re, (TC)im};
+                }
+            }
+        }
+}
+
+// ------------------------------------------------------------ launchers ----
+static int splits_for(int M, int N, int K, int chunk_hint, int *chunk) {
+    const int tiles = ceil_div(M, TM) * ceil_div(N, TN);
+    int c = chunk_hint > 0 ? chunk_hint : 0;
+    if (c <= 0) {
+        const int want = std::max(1, 512 / std::max(1, tiles));
+        c = std::max(256, ceil_div(K, want));
+    }
+    c = ceil_div(c, KT) * KT;
+    *chunk = c;
+    return std::max(1, ceil_div(K, c));
+}
+
+// Upper bound over every K' <= K: with a chunk hint the split count grows with K;
+// without one it never exceeds the work-group target 512 / tiles.
+size_t gemm_cn_part_bytes(int M, int N, int K, int elem_bytes, int chunk_hint) {
+    int c;
+    int ns = splits_for(M, N, K, chunk_hint, &c);
+    if (chunk_hint <= 0) ns = std::max(ns, std::max(1, 512 / std::max(1, ceil_div(M, TM) * ceil_div(N, TN))));
+    return (size_t)ns * M * N * elem_bytes;
+}
+
+template <typename T>
+static int cn_part(int M, int N, int K, const void *A, int64_t lda, const void *B, int64_t ldb, void *part,
+                   int chunk_hint, int *nsplit, hipStream_t st) {
+    int chunk;
+    const int ns = splits_for(M, N, K, chunk_hint, &chunk);
+    *nsplit = ns;
+    dim3 grid(ceil_div(M, TM), ceil_div(N, TN), ns);
+    KernelTimer kt("gemm_cn", st);
+    hipLaunchKernelGGL(k_gemm_cn_part<T>, grid, dim3(256), 0, st, M, N, K, chunk, static_cast<const cx<T> *>(A), lda,
+                       static_cast<const cx<T> *>(B), ldb, static_cast<cx<T> *>(part));
+    return check_launch("gemm_cn");
+}
+
+template <typename T>
+static int gemm_cn_t(int M, int N, int K, const void *A, int64_t lda, const void *B, int64_t ldb, void *C,
+                     int64_t ldc, double alpha, double beta, void *part, int chunk_hint, hipStream_t st) {
+    if (M <= 0 || N <= 0) return ABACUS_PW_OK;
+    int ns;
+    APW_TRY(cn_part<T>(M, N, K, A, lda, B, ldb, part, chunk_hint, &ns, st));
+    const int64_t tot = (int64_t)M * N;
+    KernelTimer kt("gemm_reduce", st);
+    hipLaunchKernelGGL(k_reduce<T>, dim3((unsigned)ceil_div64(tot, 256)), dim3(256), 0, st, M, N, ns,
+                       static_cast<const cx<T> *>(part), static_cast<cx<T> *>(C), ldc, alpha, beta);
+    return check_launch("gemm_reduce");
+}
+
+int gemm_cn(int prec, int M, int N, int K, const void *A, int64_t lda, const void *B, int64_t ldb, void *C,
+            int64_t ldc, double alpha, double beta, void *part, int chunk_hint, hipStream_t st) {
+    return prec == 0 ? gemm_cn_t<double>(M, N, K, A, lda, B, ldb, C, ldc, alpha, beta, part, chunk_hint, st)
+                     : gemm_cn_t<float>(M, N, K, A, lda, B, ldb, C, ldc, alpha, beta, part, chunk_hint, st);
+}
+
+template <typename T>
+static int proj_dapply_t(int M, int N, int K, const void *Bm, int64_t ldb, const void *psi, int64_t ldp,
+                         const double *dmat, const int *blo, const int *bn, const int *bdoff, void *P, void *Q,
+                         void *part, int chunk_hint, hipStream_t st) {
+    if (M <= 0 || N <= 0) return ABACUS_PW_OK;
+    int ns;
+    APW_TRY(cn_part<T>(M, N, K, Bm, ldb, psi, ldp, part, chunk_hint, &ns, st));
+    const size_t lds = (size_t)M * sizeof(cx<double>);
+    if (lds > 64 * 1024) return set_error(ABACUS_PW_EBAD_SHAPE, "too many projectors for the D-apply stage");
+    KernelTimer kt("reduce_dapply", st);
+    hipLaunchKernelGGL(k_reduce_dapply<T>, dim3(N), dim3(256), lds, st, M, ns, static_cast<const cx<T> *>(part), N,
+                       dmat, blo, bn, bdoff, static_cast<cx<T> *>(P), static_cast<cx<T> *>(Q));
+    return check_launch("reduce_dapply");
+}
+
+int proj_dapply(int prec, int M, int N, int K, const void *Bm, int64_t ldb, const void *psi, int64_t ldp,
+                const double *dmat, const int *blo, const int *bn, const int *bdoff, void *P, void *Q, void *part,
+                int chunk_hint, hipStream_t st) {
+    return prec == 0 ? proj_dapply_t<double>(M, N, K, Bm, ldb, psi, ldp, dmat, blo, bn, bdoff, P, Q, part,
+                                             chunk_hint, st)
+                     : proj_dapply_t<float>(M, N, K, Bm, ldb, psi, ldp, dmat, blo, bn, bdoff, P, Q, part,
+                                            chunk_hint, st);
+}
+
+template <typename T, typename TC>
+static int gemm_nn_t(int M, int G, int K, const void *A, int64_t lda, const void *B, int64_t ldb, void *C,
+                     int64_t ldc, double alpha, double beta, hipStream_t st) {
+    if (M <= 0 || G <= 0) return ABACUS_PW_OK;
+    dim3 grid(ceil_div(G, TN), ceil_div(M, TM));
+    KernelTimer kt("gemm_nn", st);
+    hipLaunchKernelGGL((k_gemm_nn<T, TC>), grid, dim3(256), 0, st, M, G, K, static_cast<const cx<T> *>(A), lda,
+                       static_cast<const cx<T> *>(B), ldb, static_cast<cx<TC> *>(C), ldc, alpha, beta);
+    return check_launch("gemm_nn");
+}
+
+int gemm_nn(int prec, int M, int G, int K, const void *A, int64_t lda, const void *B, int64_t ldb, void *C,
+            int64_t ldc, double alpha, double beta, hipStream_t st) {
+    return prec == 0 ? gemm_nn_t<double, double>(M, G, K, A, lda, B, ldb, C, ldc, alpha, beta, st)
+                     : gemm_nn_t<float, float>(M, G, K, A, lda, B, ldb, C, ldc, alpha, beta, st);
+}
+
+int gemm_nn_f32_into_f64(int M, int G, int K, const void *A, int64_t lda, const void *B, int64_t ldb, void *C,
+                         int64_t ldc, double alpha, double beta, hipStream_t st) {
+    return gemm_nn_t<float, double>(M, G, K, A, lda, B, ldb, C, ldc, alpha, beta, st);
+}
+
+}  // namespace apw

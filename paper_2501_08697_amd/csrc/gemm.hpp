@@ -1,0 +1,29 @@
+// Complex GEMMs on MFMA; see gemm.hip. prec: 0 complex128, 1 complex64.
+#pragma once
+
+#include "common.hpp"
+
+namespace apw {
+
+// Bytes of split-K partial sums gemm_cn / proj_dapply need.
+size_t gemm_cn_part_bytes(int M, int N, int K, int elem_bytes, int chunk_hint);
+
+// C[j*ldc + i] = alpha * sum_k conj(A[i*lda + k]) B[j*ldb + k] + beta * C[...],  i < M, j < N.
+int gemm_cn(int prec, int M, int N, int K, const void *A, int64_t lda, const void *B, int64_t ldb, void *C,
+            int64_t ldc, double alpha, double beta, void *part, int chunk_hint, hipStream_t st);
+
+// P[j][i] = <beta_i | psi_j> (M = nproj, N = bands, K = npw); Q[j][i] = sum_t D_blk(i) P[j][.].
+// P may be NULL. D-block tables as in the plan.
+int proj_dapply(int prec, int M, int N, int K, const void *Bm, int64_t ldb, const void *psi, int64_t ldp,
+                const double *dmat, const int *blo, const int *bn, const int *bdoff, void *P, void *Q, void *part,
+                int chunk_hint, hipStream_t st);
+
+// C[j*ldc + g] = alpha * sum_i A[j*lda + i] B[i*ldb + g] + beta * C[...],  j < M, g < G.
+int gemm_nn(int prec, int M, int G, int K, const void *A, int64_t lda, const void *B, int64_t ldb, void *C,
+            int64_t ldc, double alpha, double beta, hipStream_t st);
+
+// As gemm_nn with complex64 A and B accumulated into a complex128 C.
+int gemm_nn_f32_into_f64(int M, int G, int K, const void *A, int64_t lda, const void *B, int64_t ldb, void *C,
+                         int64_t ldc, double alpha, double beta, hipStream_t st);
+
+}  // namespace apw

@@ -1,0 +1,22 @@
+// Drivers behind the C entry points.
+#pragma once
+
+#include "plan.hpp"
+
+namespace apw {
+
+int default_band_batch(const Plan &P, int nb);
+int operator_copies(const abacus_pw_problem &p, Plan &P, bool need_v32, bool need_b32, hipStream_t st);
+
+// hpsi = H psi for nb bands at every k-point (packed [k][nb][npw_k]).
+int apply_h_all(const abacus_pw_problem &p, Plan &P, int prec, int nb, const void *psi, void *hpsi, hipStream_t st);
+
+// Adjoint of apply_h_all (abacus_pw_apply_h_backward).
+int apply_h_backward_all(const abacus_pw_problem &p, Plan &P, int prec, int nb, const void *psi, const void *dy,
+                         void *grad_psi, double *grad_v, double *grad_d, hipStream_t st);
+
+// Block Davidson (abacus_pw_davidson).
+int davidson_all(const abacus_pw_problem &p, Plan &P, int prec, int nb, void *psi, double *eig, double tol,
+                 int max_iter, int ndim, int *iters, double *resid, hipStream_t st);
+
+}  // namespace apw

@@ -1,0 +1,273 @@
+// Local-potential term of H psi on the real-space grid (plane-wave KS equation,
+// Sec. III.A; V_local of the pseudopotential split, Sec. II.A):
+//
+//   (V psi)(G) = (1/N) sum_j e^{-iG.r_j} V(r_j) sum_{G'} psi(G') e^{+iG'.r_j}
+//
+// computed per band as three passes over a pruned grid, all resident in LDS
+// while they transform:
+//   yz_inv  one work-group per (band, plane m1): scatter the plane's sphere points
+//           into an N2 x N3 LDS plane, inverse z transforms on the rows that hold
+//           sphere columns, inverse y transforms on every column, store the plane.
+//           Only planes m1 in [m1min, m1min + nslab) exist (the "slab").
+//   xpass   one work-group per (band, j2): load the slab rows of an N1 x N3 tile,
+//           inverse x transform, multiply by V(r), forward x transform, store the
+//           slab rows back (in place).
+//   yz_fwd  one work-group per (band, plane): forward y, forward z on the column
+//           rows, gather the sphere points, write |k+G|^2 psi + (1/N) (V psi).
+// HBM traffic per band: psi and H psi once, four passes over the slab
+// (nslab * N2 * N3 complex), V once per band tile.
+#include "fft_device.hpp"
+#include "local.hpp"
+#include "plan.hpp"
+
+namespace apw {
+
+template <typename T> __device__ __forceinline__ cx<T> czero() { return cx<T>{T(0), T(0)}; }
+
+template <int N, typename T, typename TIN>
+__global__ __launch_bounds__(256) void k_yz_inv(const cx<TIN> *__restrict__ psi, int64_t ldpsi,
+                                                const int *__restrict__ pt_off, const int *__restrict__ pt_g,
+                                                const int *__restrict__ pt_pos, const int *__restrict__ row_off,
+                                                const int *__restrict__ row_list, const cx<T> *__restrict__ tw_g,
+                                                cx<T> *__restrict__ slab, int nslab) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    cx<T> *plane = reinterpret_cast<cx<T> *>(smem);
+    cx<T> *tw = plane + N * N;
+    const int s = blockIdx.x, b = blockIdx.y;
+    const int tid = threadIdx.x, nthr = blockDim.x;
+    for (int i = tid; i < N; i += nthr) tw[i] = tw_g[i];
+    for (int i = tid; i < N * N; i += nthr) plane[i] = czero<T>();
+    __syncthreads();
+    const cx<TIN> *x = psi + b * ldpsi;
+    const int p0 = pt_off[s], p1 = pt_off[s + 1];
+    for (int p = p0 + tid; p < p1; p += nthr) plane[pt_pos[p]] = cvt<T>(x[pt_g[p]]);
+    __syncthreads();
+    const int r0 = row_off[s], nr = row_off[s + 1] - r0;
+    lds_fft<N, +1, false>(plane, nr, [=](int l) { return row_list[r0 + l] * N; }, 1, tw);
+    lds_fft<N, +1, true>(plane, N, [](int l) { return l; }, N, tw);
+    cx<T> *out = slab + ((int64_t)b * nslab + s) * (int64_t)(N * N);
+    for (int i = tid; i < N * N; i += nthr) out[i] = plane[i];
+}
+
+template <int N1, typename T, typename TV>
+__global__ __launch_bounds__(256) void k_xpass(cx<T> *__restrict__ slab, int nslab, int N2, int N3,
+                                               const int *__restrict__ row_to_slab, const TV *__restrict__ vloc,
+                                               const cx<T> *__restrict__ tw_g) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    cx<T> *tile = reinterpret_cast<cx<T> *>(smem);
+    cx<T> *tw = tile + N1 * N3;
+    const int j2 = blockIdx.x, b = blockIdx.y;
+    const int tid = threadIdx.x, nthr = blockDim.x;
+    const int64_t plane = (int64_t)N2 * N3;
+    for (int i = tid; i < N1; i += nthr) tw[i] = tw_g[i];
+    cx<T> *base = slab + (int64_t)b * nslab * plane + (int64_t)j2 * N3;
+    for (int i = tid; i < N1 * N3; i += nthr) {
+        const int r = i / N3, c = i - r * N3;
+        const int s = row_to_slab[r];
+        tile[i] = s >= 0 ? base[s * plane + c] : czero<T>();
+    }
+    __syncthreads();
+    lds_fft<N1, +1, true>(tile, N3, [](int l) { return l; }, N3, tw);
+    const TV *v = vloc + (int64_t)j2 * N3;
+    for (int i = tid; i < N1 * N3; i += nthr) {
+        const int r = i / N3, c = i - r * N3;
+        tile[i] = tile[i] * static_cast<T>(v[(int64_t)r * plane + c]);
+    }
+    __syncthreads();
+    lds_fft<N1, -1, true>(tile, N3, [](int l) { return l; }, N3, tw);
+    for (int i = tid; i < N1 * N3; i += nthr) {
+        const int r = i / N3, c = i - r * N3;
+        const int s = row_to_slab[r];
+        if (s >= 0) base[s * plane + c] = tile[i];
+    }
+}
+
+template <int N, typename T, typename TIO>
+__global__ __launch_bounds__(256) void k_yz_fwd(const cx<T> *__restrict__ slab, int nslab,
+                                                const int *__restrict__ pt_off, const int *__restrict__ pt_g,
+                                                const int *__restrict__ pt_pos, const int *__restrict__ row_off,
+                                                const int *__restrict__ row_list, const cx<T> *__restrict__ tw_g,
+                                                const double *__restrict__ kin, const cx<TIO> *__restrict__ psi,
+                                                cx<TIO> *__restrict__ hpsi, int64_t ld, double inv_n) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    cx<T> *plane = reinterpret_cast<cx<T> *>(smem);
+    cx<T> *tw = plane + N * N;
+    const int s = blockIdx.x, b = blockIdx.y;
+    const int tid = threadIdx.x, nthr = blockDim.x;
+    for (int i = tid; i < N; i += nthr) tw[i] = tw_g[i];
+    const cx<T> *in = slab + ((int64_t)b * nslab + s) * (int64_t)(N * N);
+    for (int i = tid; i < N * N; i += nthr) plane[i] = in[i];
+    __syncthreads();
+    lds_fft<N, -1, true>(plane, N, [](int l) { return l; }, N, tw);
+    const int r0 = row_off[s], nr = row_off[s + 1] - r0;
+    lds_fft<N, -1, false>(plane, nr, [=](int l) { return row_list[r0 + l] * N; }, 1, tw);
+    const cx<TIO> *x = psi + b * ld;
+    cx<TIO> *y = hpsi + b * ld;
+    const int p0 = pt_off[s], p1 = pt_off[s + 1];
+    const TIO sc = static_cast<TIO>(inv_n);
+    for (int p = p0 + tid; p < p1; p += nthr) {
+        const int g = pt_g[p];
+        const cx<TIO> v = cvt<TIO>(plane[pt_pos[p]]);
+        const TIO kg = static_cast<TIO>(kin[g]);
+        const cx<TIO> xg = x[g];
+        y[g] = cx<TIO>{kg * xg.re + sc * v.re, kg * xg.im + sc * v.im};
+    }
+}
+
+// ------------------------------------------------------------ launchers ----
+template <typename K> static int allow_lds(K kernel, size_t bytes) {
+    APW_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(kernel),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes));
+    return ABACUS_PW_OK;
+}
+
+constexpr size_t kLdsLimit = 160 * 1024;
+
+template <int N, typename T, typename TIO>
+static int launch_yz(bool inverse, const Plan &P, const KTables &K, const void *psi, void *hpsi, void *slab,
+                     int nbands, hipStream_t st) {
+    const size_t lds = (size_t)(N * N + N) * sizeof(cx<T>);
+    if (lds > kLdsLimit) return set_error(ABACUS_PW_EBAD_FFT_SIZE, "y-z plane does not fit in LDS at this precision");
+    const cx<T> *tw = static_cast<const cx<T> *>(sizeof(T) == 8 ? P.tw64[2] : P.tw32[2]);
+    dim3 grid(P.nslab, nbands), block(256);
+    if (inverse) {
+        static bool once = false;
+        if (!once) {
+            APW_TRY(allow_lds(k_yz_inv<N, T, TIO>, lds));
+            once = true;
+        }
+        KernelTimer kt("yz_inv", st);
+        hipLaunchKernelGGL((k_yz_inv<N, T, TIO>), grid, block, lds, st, static_cast<const cx<TIO> *>(psi),
+                           (int64_t)K.npw, K.pt_off, K.pt_g, K.pt_pos, K.row_off, K.row_list, tw,
+                           static_cast<cx<T> *>(slab), P.nslab);
+        return check_launch("yz_inv");
+    }
+    static bool once = false;
+    if (!once) {
+        APW_TRY(allow_lds(k_yz_fwd<N, T, TIO>, lds));
+        once = true;
+    }
+    KernelTimer kt("yz_fwd", st);
+    hipLaunchKernelGGL((k_yz_fwd<N, T, TIO>), grid, block, lds, st, static_cast<const cx<T> *>(slab), P.nslab,
+                       K.pt_off, K.pt_g, K.pt_pos, K.row_off, K.row_list, tw, K.kin,
+                       static_cast<const cx<TIO> *>(psi), static_cast<cx<TIO> *>(hpsi), (int64_t)K.npw,
+                       1.0 / (double)P.N);
+    return check_launch("yz_fwd");
+}
+
+template <int N1, typename T>
+static int launch_x(const Plan &P, const void *vloc, void *slab, int nbands, hipStream_t st) {
+    const size_t lds = (size_t)(N1 * P.N3 + N1) * sizeof(cx<T>);
+    if (lds > kLdsLimit) return set_error(ABACUS_PW_EBAD_FFT_SIZE, "x-z tile does not fit in LDS at this precision");
+    static size_t allowed = 0;
+    if (lds > allowed) {
+        APW_TRY(allow_lds(k_xpass<N1, T, T>, kLdsLimit));
+        allowed = kLdsLimit;
+    }
+    const cx<T> *tw = static_cast<const cx<T> *>(sizeof(T) == 8 ? P.tw64[0] : P.tw32[0]);
+    KernelTimer kt("xpass", st);
+    hipLaunchKernelGGL((k_xpass<N1, T, T>), dim3(P.N2, nbands), dim3(256), lds, st, static_cast<cx<T> *>(slab),
+                       P.nslab, P.N2, P.N3, P.row_to_slab, static_cast<const T *>(vloc), tw);
+    return check_launch("xpass");
+}
+
+#define APW_LENGTHS(X) \
+    X(8) X(12) X(16) X(18) X(20) X(24) X(27) X(30) X(32) X(36) X(40) X(45) X(48) X(54) X(60) X(64) X(72) X(80) \
+    X(81) X(90) X(96) X(100) X(108) X(120) X(128)
+
+int local_length_supported(int n) {
+    switch (n) {
+#define APW_CASE(n) case n:
+        APW_LENGTHS(APW_CASE)
+#undef APW_CASE
+        return 1;
+        default:
+            return 0;
+    }
+}
+
+template <typename T, typename TIO>
+static int dispatch_yz(bool inverse, const Plan &P, const KTables &K, const void *psi, void *hpsi, void *slab,
+                       int nbands, hipStream_t st) {
+    switch (P.N3) {
+#define APW_CASE(n) \
+    case n: return launch_yz<n, T, TIO>(inverse, P, K, psi, hpsi, slab, nbands, st);
+        APW_LENGTHS(APW_CASE)
+#undef APW_CASE
+        default:
+            return set_error(ABACUS_PW_EBAD_FFT_SIZE, "unsupported grid length");
+    }
+}
+
+template <typename T>
+static int dispatch_x(const Plan &P, const void *vloc, void *slab, int nbands, hipStream_t st) {
+    switch (P.N1) {
+#define APW_CASE(n) \
+    case n: return launch_x<n, T>(P, vloc, slab, nbands, st);
+        APW_LENGTHS(APW_CASE)
+#undef APW_CASE
+        default:
+            return set_error(ABACUS_PW_EBAD_FFT_SIZE, "unsupported grid length");
+    }
+}
+
+int local_supported(const Plan &P, int fft_prec) {
+    if (!local_length_supported(P.N1) || !local_length_supported(P.N2) || !local_length_supported(P.N3))
+        return set_error(ABACUS_PW_EBAD_FFT_SIZE, "grid length without a transform");
+    if (P.N2 != P.N3) return set_error(ABACUS_PW_EBAD_FFT_SIZE, "the plane transform needs N2 == N3");
+    const size_t cb = fft_prec == 0 ? 16 : 8;
+    if ((size_t)(P.N3 * P.N3 + P.N3) * cb > kLdsLimit || (size_t)(P.N1 * P.N3 + P.N1) * cb > kLdsLimit)
+        return set_error(ABACUS_PW_EBAD_FFT_SIZE, "grid plane too large for LDS at this precision");
+    return ABACUS_PW_OK;
+}
+
+size_t local_slab_bytes(const Plan &P, int fft_prec, int nbands) {
+    return (size_t)nbands * (size_t)P.nslab * (size_t)P.N2 * (size_t)P.N3 * (fft_prec == 0 ? 16 : 8);
+}
+
+int local_term(const Plan &P, int kidx, int fft_prec, int io_prec, const void *vloc, const void *psi, void *hpsi,
+               int nb, void *slab, int band_batch, hipStream_t st) {
+    const KTables &K = P.k[kidx];
+    const size_t ib = io_prec == 0 ? 16 : 8;
+    for (int b0 = 0; b0 < nb; b0 += band_batch) {
+        const int nbb = nb - b0 < band_batch ? nb - b0 : band_batch;
+        const char *x = static_cast<const char *>(psi) + (size_t)b0 * K.npw * ib;
+        char *y = static_cast<char *>(hpsi) + (size_t)b0 * K.npw * ib;
+        if (fft_prec == 0) {
+            APW_TRY((dispatch_yz<double, double>(true, P, K, x, nullptr, slab, nbb, st)));
+            APW_TRY((dispatch_x<double>(P, vloc, slab, nbb, st)));
+            APW_TRY((dispatch_yz<double, double>(false, P, K, x, y, slab, nbb, st)));
+        } else if (io_prec == 1) {
+            APW_TRY((dispatch_yz<float, float>(true, P, K, x, nullptr, slab, nbb, st)));
+            APW_TRY((dispatch_x<float>(P, vloc, slab, nbb, st)));
+            APW_TRY((dispatch_yz<float, float>(false, P, K, x, y, slab, nbb, st)));
+        } else {
+            APW_TRY((dispatch_yz<float, double>(true, P, K, x, nullptr, slab, nbb, st)));
+            APW_TRY((dispatch_x<float>(P, vloc, slab, nbb, st)));
+            APW_TRY((dispatch_yz<float, double>(false, P, K, x, y, slab, nbb, st)));
+        }
+    }
+    return ABACUS_PW_OK;
+}
+
+}  // namespace apw
+
+namespace apw {
+
+// Host view of the LDS split (N = A * B) of every compiled length.
+int lds_split_host(int n, int *a, int *b) {
+    switch (n) {
+#define APW_CASE(n)              \
+    case n:                      \
+        *a = LdsSplit<n>::A;     \
+        *b = LdsSplit<n>::B;     \
+        return 1;
+        APW_LENGTHS(APW_CASE)
+#undef APW_CASE
+        default:
+            *a = *b = 0;
+            return 0;
+    }
+}
+
+}  // namespace apw

@@ -1,0 +1,21 @@
+// Local-potential term of H psi (grid transforms); see local.hip.
+#pragma once
+
+#include "plan.hpp"
+
+namespace apw {
+
+// 1 when a transform of length n is compiled in.
+int local_length_supported(int n);
+// OK when the plan's grid can run at fft_prec (0 = FP64, 1 = FP32), else EBAD_FFT_SIZE.
+int local_supported(const Plan &P, int fft_prec);
+// Slab work space for nbands bands.
+size_t local_slab_bytes(const Plan &P, int fft_prec, int nbands);
+
+// hpsi = |k+G|^2 psi + (V psi) for nb bands of k-point kidx ([nb][npw_k] blocks).
+// fft_prec: 0 FP64, 1 FP32 transforms. io_prec: 0 complex128, 1 complex64 psi/hpsi.
+// vloc: float64 grid for fft_prec 0, float32 for 1. slab: local_slab_bytes(band_batch).
+int local_term(const Plan &P, int kidx, int fft_prec, int io_prec, const void *vloc, const void *psi, void *hpsi,
+               int nb, void *slab, int band_batch, hipStream_t st);
+
+}  // namespace apw

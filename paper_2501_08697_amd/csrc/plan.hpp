@@ -1,0 +1,96 @@
+// The plan: everything derived once from a problem's geometry (grid, sphere
+// maps, kinetic factors, twiddles, D-block tables) plus the work space the
+// kernels use. Built by plan.cpp, read by every module.
+#pragma once
+
+#include <cstdint>
+#include <vector>
+
+#include "common.hpp"
+
+namespace apw {
+
+// Per-k device tables for the sphere <-> grid maps.
+//
+// The local term works plane by plane: plane s holds the sphere points whose
+// first Miller index is m1 = m1min + s. For plane s:
+//   points  [pt_off[s], pt_off[s+1])  with  pt_g   = index in the k's sphere order,
+//                                           pt_pos = LDS slot perm2(i2) * N3 + perm3(i3)
+//   rows    [row_off[s], row_off[s+1]) with row_list = slot row perm2(i2) of every z column
+// where i = m mod N and perm is the digit-permuted slot of the LDS transform.
+struct KTables {
+    int npw = 0;
+    int64_t pw_off = 0;          // sum of npw over the previous k-points
+    const int *pt_off = nullptr;
+    const int *pt_g = nullptr;
+    const int *pt_pos = nullptr;
+    const int *row_off = nullptr;
+    const int *row_list = nullptr;
+    const double *kin = nullptr;   // |k+G|^2 in sphere order
+    const float *kin32 = nullptr;
+};
+
+struct DeviceBuffer {
+    void *ptr = nullptr;
+    size_t bytes = 0;
+    ~DeviceBuffer();
+    int ensure(size_t n);   // grow (never shrink); contents are not preserved
+    template <typename T> T *as() const { return static_cast<T *>(ptr); }
+};
+
+struct Plan {
+    // geometry
+    double lattice[9];
+    double recip[9];
+    int N1 = 0, N2 = 0, N3 = 0;
+    int64_t N = 0;
+    int nslab = 0, m1min = 0;
+    int nk = 0;
+    std::vector<int> npw;
+    std::vector<int64_t> pw_off;   // [nk+1]
+    int64_t npw_total = 0;
+    int max_npw = 0;
+    std::vector<KTables> k;
+    int nproj = 0, natom = 0;
+    std::vector<int> proj_atom_offset;
+
+    // device tables
+    DeviceBuffer tables;          // all int/double geometry tables, one allocation
+    const int *row_to_slab = nullptr;     // [N1]: slab index of LDS row perm1(i1), or -1
+    const void *tw64[3] = {nullptr, nullptr, nullptr};   // per axis, cx<double>[N_i]
+    const void *tw32[3] = {nullptr, nullptr, nullptr};   // per axis, cx<float>[N_i]
+    // D application: for projector i, its atom block [blk_lo[i], blk_lo[i]+blk_n[i]) and
+    // the offset of that block in dmat.
+    const int *proj_blk_lo = nullptr;
+    const int *proj_blk_n = nullptr;
+    const int *proj_blk_doff = nullptr;
+    int64_t dmat_len = 0;
+
+    // reduced-precision copies of operator data (refreshed unless STATIC)
+    DeviceBuffer vloc32;
+    DeviceBuffer beta32;      // complex64 beta
+    DeviceBuffer betabf;      // bf16 planar beta (re block, im block) per k
+    const void *vloc32_src = nullptr, *beta32_src = nullptr, *betabf_src = nullptr;
+
+    // work space
+    DeviceBuffer slab;        // [band_batch][nslab][N2][N3] complex
+    DeviceBuffer gemm_part;   // split-K partial sums
+    DeviceBuffer proj;        // P = B^H psi  [nb][nproj] complex128 (or complex64)
+    DeviceBuffer projq;       // Q = D P
+    DeviceBuffer proj2;       // second projection (backward)
+    DeviceBuffer projq2;
+    DeviceBuffer gradv_part;  // band-group partial sums of grad V
+    DeviceBuffer tmp_io;      // precision staging
+};
+
+// Global tuning knobs (abacus_pw_set_tuning).
+extern int g_band_batch;
+extern int g_splitk_chunk;
+
+// Looks up or builds the plan for a problem (validates it on build).
+int get_plan(const abacus_pw_problem *p, Plan **out);
+
+// Host-side checks of a problem that do not need a plan.
+int validate_problem_shallow(const abacus_pw_problem *p);
+
+}  // namespace apw

@@ -1,0 +1,124 @@
+"""The C-ABI library on a machine without a GPU: it loads, exports every
+entry point declared in include/abacus_pw.h, and rejects invalid problems on
+the host before touching the device."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2501_08697_amd import binding as B
+from paper_2501_08697_amd import workload as W
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+FAKE = 0x1000   # never dereferenced: validation fails before any device access
+
+
+def header_functions():
+    txt = open(os.path.join(ROOT, "include", "abacus_pw.h")).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(abacus_pw_[a-z_0-9]+)\s*\(", txt)))
+
+
+def test_library_exports_every_declared_function():
+    lib = B.lib()
+    names = header_functions()
+    assert len(names) >= 9
+    for n in names:
+        assert hasattr(lib, n), n
+    assert set(names) == set(B.EXPORTS)
+
+
+def test_fft_lengths():
+    for n in (8, 12, 16, 32, 72, 96, 120, 128):
+        assert B.fft_supported(n)
+    for n in (7, 14, 11, 256, 0):
+        assert not B.fft_supported(n)
+
+
+class Fake:
+    """A CProblem with host arrays from a generated problem and fake device pointers."""
+
+    def __init__(self, prob):
+        self.kpts = np.ascontiguousarray(prob.kpts)
+        self.npw = np.ascontiguousarray(prob.npw, dtype=np.int32)
+        self.miller = np.ascontiguousarray(prob.miller, dtype=np.int32)
+        self.offs = np.ascontiguousarray(prob.proj_atom_offset, dtype=np.int32)
+        s = B.CProblem()
+        s.lattice[:] = list(np.asarray(prob.lattice).reshape(-1))
+        s.fft[:] = list(prob.fft)
+        s.ecutwfc = prob.ecut
+        s.nk = prob.nk
+        s.kpts, s.npw, s.miller = self.kpts.ctypes.data, self.npw.ctypes.data, self.miller.ctypes.data
+        s.vloc = FAKE
+        s.nproj, s.natom = prob.nproj, prob.natom
+        s.proj_atom_offset = self.offs.ctypes.data
+        s.beta, s.dmat = FAKE, FAKE
+        self.s = s
+
+    def apply(self, prec=0, nb=1):
+        return B.lib().abacus_pw_apply_h(C.byref(self.s), prec, nb, FAKE, FAKE + 64, None)
+
+
+@pytest.fixture()
+def prob():
+    return W.make_problem(W.tiny_config(fft=12, ecut=12.0, nb=2))
+
+
+def code_name(code):
+    return B.ERRORS.get(code, code)
+
+
+def test_rejects_null_and_shape(prob):
+    f = Fake(prob)
+    assert code_name(B.lib().abacus_pw_apply_h(None, 0, 1, FAKE, FAKE + 64, None)) == "ENULL_ARG"
+    assert code_name(B.lib().abacus_pw_apply_h(C.byref(f.s), 0, 1, None, FAKE, None)) == "ENULL_ARG"
+    assert code_name(B.lib().abacus_pw_apply_h(C.byref(f.s), 0, 1, FAKE, FAKE, None)) == "EBAD_SHAPE"
+    assert code_name(f.apply(nb=0)) == "EBAD_SHAPE"
+    f.s.nk = 0
+    assert code_name(f.apply()) == "EBAD_SHAPE"
+
+
+def test_rejects_bad_precision(prob):
+    assert code_name(Fake(prob).apply(prec=7)) == "EBAD_PRECISION"
+
+
+def test_rejects_bad_offsets(prob):
+    f = Fake(prob)
+    f.offs[-1] += 1
+    assert code_name(f.apply()) == "EBAD_SHAPE"
+
+
+def test_rejects_unsupported_grid(prob):
+    f = Fake(prob)
+    f.s.fft[0] = 14
+    assert code_name(f.apply()) == "EBAD_FFT_SIZE"
+
+
+def test_rejects_sphere_not_fitting():
+    prob = W.make_problem(W.tiny_config(fft=12, ecut=20.0, nb=1))   # |m| reaches 4: needs N >= 9
+    f = Fake(prob)
+    f.s.fft[:] = [8, 8, 8]
+    assert code_name(f.apply()) == "EBAD_FFT_SIZE"
+
+
+def test_rejects_duplicate_and_outside_sphere(prob):
+    f = Fake(prob)
+    f.miller[5] = f.miller[6]
+    assert code_name(f.apply()) == "EBAD_SPHERE"
+    g = Fake(prob)
+    g.s.ecutwfc = prob.ecut * 0.5
+    assert code_name(g.apply()) == "EBAD_SPHERE"
+
+
+def test_error_message_is_set(prob):
+    f = Fake(prob)
+    f.miller[5] = f.miller[6]
+    f.apply()
+    assert "duplicate" in B.last_error()
+
+
+def test_tuning_rejects_negative():
+    assert code_name(B.lib().abacus_pw_set_tuning(-1, 0)) == "EBAD_SHAPE"
+    assert B.lib().abacus_pw_set_tuning(0, 0) == 0
