@@ -1,0 +1,263 @@
+"""Benchmark of the plane-wave H psi hot path on one MI355X.
+
+Workload (the FP64-vs-FP32 H psi case): simple-cubic cell a = 20.5 bohr,
+ecutwfc = 30 Ry (23,847 plane waves at Gamma), 72^3 grid, 64 atoms x 4
+Kleinman-Bylander projectors (s + p), 128 bands, seeded synthetic inputs.
+
+One step = one H psi over all 128 bands in FP64: local term (three LDS
+transform passes on the grid) and nonlocal term (projection GEMM, D blocks,
+accumulation GEMM), inputs resident in HBM. `value` = band-applies per second
+= 128 * steps / time. The same JSON line carries the FP32 rate and its speedup,
+block Davidson time per k-point in FP64 (and mixed precision) to a 1e-8
+residual, the roofline of the dominant kernel (per-kernel times from HIP events
+recorded on the library's stream during the timed region), and the FP64 CPU
+oracle timed on this host.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-davidson]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import re
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0           # MI355X HBM3E, datasheet
+FP64_PEAK_TFLOPS = 78.6         # MI355X dense FP64 (vector = matrix)
+FP32_PEAK_TFLOPS = 157.3
+WORKLOAD = "C2"
+WORKLOAD_DESC = ("cubic a=20.5 bohr, ecutwfc=30 Ry, 23847 PW, 72^3 grid, Gamma, 64 atoms x 4 KB projectors, "
+                 "128 bands, complex128")
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-davidson", action="store_true")
+    return ap.parse_args()
+
+
+def kernel_model(name, prob, bb, nb):
+    """Algorithmic (bytes, flops) of ONE launch of a library kernel at this workload.
+
+    cb = 16 bytes per complex128. S = nslab * N2 * N3 (the slab: grid planes that
+    hold sphere points), npw sphere points; a band-batch launch covers bb bands.
+      yz_inv : bb * cb * (npw + S)          read psi, write the slab planes
+      xpass  : bb * cb * 2 S + 8 N          slab in and out, V once
+      yz_fwd : bb * cb * (S + 2 npw)        slab in, psi in (kinetic), H psi out
+      gemm_cn: flops 8 nproj nb npw; bytes cb (nproj + nb) npw
+      gemm_nn: flops 8 nb npw nproj; bytes cb (nproj npw + 2 nb npw)
+    """
+    cb = 16
+    n1, n2, n3 = prob.fft
+    N = n1 * n2 * n3
+    npw = int(prob.npw[0])
+    m1 = prob.miller[:, 0]
+    S = (int(m1.max()) - int(m1.min()) + 1) * n2 * n3
+    npj = prob.nproj
+    if name == "yz_inv":
+        return bb * cb * (npw + S), 0
+    if name == "xpass":
+        return bb * cb * 2 * S + 8 * N, 0
+    if name == "yz_fwd":
+        return bb * cb * (S + 2 * npw), 0
+    if name == "gemm_cn":
+        return cb * (npj + nb) * npw, 8 * npj * nb * npw
+    if name == "gemm_nn":
+        return cb * (npj * npw + 2 * nb * npw), 8 * nb * npw * npj
+    return None, None
+
+
+def source_hash(paths):
+    h = hashlib.sha256()
+    for p in paths:
+        with open(os.path.join(ROOT, p), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+KERNEL_SOURCES = {
+    "yz_inv": ["paper_2501_08697_amd/csrc/local.hip", "paper_2501_08697_amd/csrc/fft_device.hpp"],
+    "xpass": ["paper_2501_08697_amd/csrc/local.hip", "paper_2501_08697_amd/csrc/fft_device.hpp"],
+    "yz_fwd": ["paper_2501_08697_amd/csrc/local.hip", "paper_2501_08697_amd/csrc/fft_device.hpp"],
+    "gemm_cn": ["paper_2501_08697_amd/csrc/gemm.hip"],
+    "gemm_nn": ["paper_2501_08697_amd/csrc/gemm.hip"],
+}
+
+
+def measured_traffic(kernel):
+    """HBM bytes per launch from the committed counter summary, if it matches the current source."""
+    path = os.path.join(ROOT, "profiles", f"traffic_{kernel}_{WORKLOAD}.txt")
+    if not os.path.exists(path):
+        return None
+    txt = open(path).read()
+    m = re.search(r"source_hash:\s*(\w+)", txt)
+    b = re.search(r"hbm_bytes_per_launch:\s*([0-9.eE+]+)", txt)
+    if not m or not b or m.group(1) != source_hash(KERNEL_SOURCES[kernel]):
+        return None
+    return float(b.group(1))
+
+
+def cpu_baseline(prob):
+    import oracle
+    nb = prob.nb
+    t0 = time.perf_counter()
+    oracle.apply_h(prob, prob.psi, nb=nb)
+    dt = time.perf_counter() - t0
+    return {"value": nb / dt, "unit": "band-applies/s", "cores": oracle.num_threads(), "kind": "oracle",
+            "sample": f"one FP64 H psi over all {nb} bands of the benchmark workload ({dt:.2f} s wall)"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); multi-GPU sharding is design-only.",
+              file=sys.stderr)
+        sys.exit(2)
+    import torch
+
+    from paper_2501_08697_amd import binding as B
+    from paper_2501_08697_amd import workload as W
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = torch.device("cuda:0")
+    prob = W.make_problem(WORKLOAD)
+    nb = prob.nb
+    dp = B.DeviceProblem(prob, device=dev)
+    x64 = torch.from_numpy(prob.psi).to(dev)
+    x32 = x64.to(torch.complex64)
+    y64 = torch.empty_like(x64)
+    y32 = torch.empty_like(x32)
+    stream = torch.cuda.current_stream()
+
+    def run(prec, x, y, steps):
+        for _ in range(steps):
+            B.apply_h(dp, x, prec, out=y)
+
+    # warm-up (builds the plan, allocates work space)
+    run(B.FP64, x64, y64, args.warmup)
+    run(B.FP32, x32, y32, args.warmup)
+    torch.cuda.synchronize()
+
+    # timed FP64 region, per-kernel HIP events recorded on the library's stream
+    B.profile_read()
+    B.profile_enable(True)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    run(B.FP64, x64, y64, args.steps)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    B.profile_enable(False)
+    kern = B.profile_read()
+    ms64 = e0.elapsed_time(e1) / args.steps
+
+    # clean FP64 and FP32 regions (no per-kernel events)
+    def timed(prec, x, y):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        a.record(stream)
+        run(prec, x, y, args.steps)
+        b.record(stream)
+        torch.cuda.synchronize()
+        return a.elapsed_time(b) / args.steps
+
+    ms64_clean = timed(B.FP64, x64, y64)
+    ms32 = timed(B.FP32, x32, y32)
+
+    # dominant kernel and its roofline
+    bb = min(nb, 32)
+    rows = {}
+    for name, (n, tot_ms) in kern.items():
+        avg = tot_ms / n
+        by, fl = kernel_model(name, prob, bb, nb)
+        rows[name] = {"launches_per_step": n / args.steps, "avg_ms": avg, "share": tot_ms / (ms64 * args.steps),
+                      "alg_bytes": by, "alg_flops": fl}
+    dom = max(rows, key=lambda k: rows[k]["avg_ms"] * rows[k]["launches_per_step"])
+    d = rows[dom]
+    if d["alg_flops"]:
+        achieved = d["alg_flops"] / (d["avg_ms"] * 1e-3) / 1e12
+        roof = {"bound": "mfma", "achieved": achieved, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+                "frac": achieved / FP64_PEAK_TFLOPS}
+    else:
+        achieved = d["alg_bytes"] / (d["avg_ms"] * 1e-3) / 1e9
+        roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": achieved / HBM_PEAK_GBS}
+    roof["kernel"] = dom
+    roof["traffic"] = measured_traffic(dom)
+    for r in rows.values():
+        if r["alg_flops"]:
+            r["tflops"] = r["alg_flops"] / (r["avg_ms"] * 1e-3) / 1e12
+        elif r["alg_bytes"]:
+            r["gbs"] = r["alg_bytes"] / (r["avg_ms"] * 1e-3) / 1e9
+
+    out = {
+        "metric": "Hψ band-applies/s, Davidson time/k-point vs plain FP64; % HBM & MFMA peak",
+        "value": nb / (ms64 * 1e-3),
+        "unit": "band-applies/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms64,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"{WORKLOAD}: {WORKLOAD_DESC}", "bands": nb, "npw": int(prob.npw[0]),
+                   "fft": list(prob.fft), "nproj": prob.nproj, "kpoints": prob.nk},
+        "roofline": roof,
+        "fp64_ms_per_step_without_kernel_events": ms64_clean,
+        "fp32": {"ms_per_step": ms32, "band_applies_per_s": nb / (ms32 * 1e-3), "speedup_vs_fp64": ms64_clean / ms32},
+        "kernels": rows,
+    }
+
+    if not args.no_davidson:
+        out["davidson"] = davidson_times(B, W, dev)
+
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(prob)
+    print(json.dumps(out), flush=True)
+
+
+def davidson_times(B, W, dev):
+    """Block Davidson on the benchmark workload to a 1e-8 residual, FP64 and mixed."""
+    import torch
+    res = {}
+    prob = W.make_problem(WORKLOAD)
+    dp = B.DeviceProblem(prob, device=dev)
+    for name, prec in (("fp64", B.FP64), ("mixed_fp32", B.MIXED_FP32)):
+        x = torch.from_numpy(prob.psi).to(dev)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        try:
+            eig, r, its, st = B.davidson(dp, x, tol=1e-8, max_iter=200, precision=prec)
+        except B.AbacusPwError as e:
+            res[name] = {"error": str(e)}
+            continue
+        dt = time.perf_counter() - t0
+        res[name] = {"s_per_kpoint": dt / prob.nk, "iterations": int(its[0]), "max_resid": float(r.max()),
+                     "converged": st == 0, "lowest": float(eig[0, 0]), "highest": float(eig[0, -1])}
+        res[name + "_eig"] = eig[0].tolist()
+    if "fp64_eig" in res and "mixed_fp32_eig" in res:
+        res["mixed_vs_fp64_max_eig_diff"] = float(np.max(np.abs(np.array(res["fp64_eig"]) -
+                                                               np.array(res["mixed_fp32_eig"]))))
+        res["mixed_speedup"] = res["fp64"]["s_per_kpoint"] / res["mixed_fp32"]["s_per_kpoint"]
+    res.pop("fp64_eig", None)
+    res.pop("mixed_fp32_eig", None)
+    return res
+
+
+if __name__ == "__main__":
+    main()
