@@ -24,8 +24,12 @@ namespace apw {
 
 template <typename T> __device__ __forceinline__ cx<T> czero() { return cx<T>{T(0), T(0)}; }
 
+constexpr int kMaxT3 = 32;     // widest j3 tile of the x pass
+constexpr int kXBands = 4;     // bands per x-pass work-group
+constexpr int kYzThreads = 512; // threads of a y-z plane work-group
+
 template <int N, typename T, typename TIN>
-__global__ __launch_bounds__(256) void k_yz_inv(const cx<TIN> *__restrict__ psi, int64_t ldpsi,
+__global__ __launch_bounds__(kYzThreads) void k_yz_inv(const cx<TIN> *__restrict__ psi, int64_t ldpsi,
                                                 const int *__restrict__ pt_off, const int *__restrict__ pt_g,
                                                 const int *__restrict__ pt_pos, const int *__restrict__ row_off,
                                                 const int *__restrict__ row_list, const cx<T> *__restrict__ tw_g,
@@ -49,41 +53,60 @@ __global__ __launch_bounds__(256) void k_yz_inv(const cx<TIN> *__restrict__ psi,
     for (int i = tid; i < N * N; i += nthr) out[i] = plane[i];
 }
 
+// One work-group per (j2, a tile of T3 consecutive j3 columns, a group of bands).
+// V of the tile is read once into registers and reused for every band of the group.
 template <int N1, typename T, typename TV>
-__global__ __launch_bounds__(256) void k_xpass(cx<T> *__restrict__ slab, int nslab, int N2, int N3,
-                                               const int *__restrict__ row_to_slab, const TV *__restrict__ vloc,
-                                               const cx<T> *__restrict__ tw_g) {
+__global__ __launch_bounds__(256) void k_xpass(cx<T> *__restrict__ slab, int nslab, int N2, int N3, int T3, int nt3,
+                                               int nbands, int bpw, const int *__restrict__ row_to_slab,
+                                               const TV *__restrict__ vloc, const cx<T> *__restrict__ tw_g) {
+    constexpr int MAXV = (N1 * kMaxT3 + 255) / 256;
     extern __shared__ __align__(16) unsigned char smem[];
     cx<T> *tile = reinterpret_cast<cx<T> *>(smem);
-    cx<T> *tw = tile + N1 * N3;
-    const int j2 = blockIdx.x, b = blockIdx.y;
+    cx<T> *tw = tile + N1 * T3;
+    const int j2 = blockIdx.x / nt3, c0 = (blockIdx.x - j2 * nt3) * T3;
+    const int w3 = min(T3, N3 - c0);
+    const int b0 = blockIdx.y * bpw, b1 = min(nbands, b0 + bpw);
     const int tid = threadIdx.x, nthr = blockDim.x;
     const int64_t plane = (int64_t)N2 * N3;
+    const int ntile = N1 * w3;
     for (int i = tid; i < N1; i += nthr) tw[i] = tw_g[i];
-    cx<T> *base = slab + (int64_t)b * nslab * plane + (int64_t)j2 * N3;
-    for (int i = tid; i < N1 * N3; i += nthr) {
-        const int r = i / N3, c = i - r * N3;
-        const int s = row_to_slab[r];
-        tile[i] = s >= 0 ? base[s * plane + c] : czero<T>();
+    T vreg[MAXV];
+#pragma unroll
+    for (int q = 0; q < MAXV; ++q) {
+        const int i = tid + q * 256;
+        vreg[q] = T(0);
+        if (i < ntile) {
+            const int r = i / w3, c = i - r * w3;
+            vreg[q] = static_cast<T>(vloc[(int64_t)r * plane + (int64_t)j2 * N3 + c0 + c]);
+        }
     }
-    __syncthreads();
-    lds_fft<N1, +1, true>(tile, N3, [](int l) { return l; }, N3, tw);
-    const TV *v = vloc + (int64_t)j2 * N3;
-    for (int i = tid; i < N1 * N3; i += nthr) {
-        const int r = i / N3, c = i - r * N3;
-        tile[i] = tile[i] * static_cast<T>(v[(int64_t)r * plane + c]);
-    }
-    __syncthreads();
-    lds_fft<N1, -1, true>(tile, N3, [](int l) { return l; }, N3, tw);
-    for (int i = tid; i < N1 * N3; i += nthr) {
-        const int r = i / N3, c = i - r * N3;
-        const int s = row_to_slab[r];
-        if (s >= 0) base[s * plane + c] = tile[i];
+    for (int b = b0; b < b1; ++b) {
+        cx<T> *base = slab + (int64_t)b * nslab * plane + (int64_t)j2 * N3 + c0;
+        for (int i = tid; i < ntile; i += nthr) {
+            const int r = i / w3, c = i - r * w3;
+            const int s = row_to_slab[r];
+            tile[i] = s >= 0 ? base[s * plane + c] : czero<T>();
+        }
+        __syncthreads();
+        lds_fft<N1, +1, true>(tile, w3, [](int l) { return l; }, w3, tw);
+#pragma unroll
+        for (int q = 0; q < MAXV; ++q) {
+            const int i = tid + q * 256;
+            if (i < ntile) tile[i] = tile[i] * vreg[q];
+        }
+        __syncthreads();
+        lds_fft<N1, -1, true>(tile, w3, [](int l) { return l; }, w3, tw);
+        for (int i = tid; i < ntile; i += nthr) {
+            const int r = i / w3, c = i - r * w3;
+            const int s = row_to_slab[r];
+            if (s >= 0) base[s * plane + c] = tile[i];
+        }
+        __syncthreads();
     }
 }
 
 template <int N, typename T, typename TIO>
-__global__ __launch_bounds__(256) void k_yz_fwd(const cx<T> *__restrict__ slab, int nslab,
+__global__ __launch_bounds__(kYzThreads) void k_yz_fwd(const cx<T> *__restrict__ slab, int nslab,
                                                 const int *__restrict__ pt_off, const int *__restrict__ pt_g,
                                                 const int *__restrict__ pt_pos, const int *__restrict__ row_off,
                                                 const int *__restrict__ row_list, const cx<T> *__restrict__ tw_g,
@@ -129,7 +152,7 @@ static int launch_yz(bool inverse, const Plan &P, const KTables &K, const void *
     const size_t lds = (size_t)(N * N + N) * sizeof(cx<T>);
     if (lds > kLdsLimit) return set_error(ABACUS_PW_EBAD_FFT_SIZE, "y-z plane does not fit in LDS at this precision");
     const cx<T> *tw = static_cast<const cx<T> *>(sizeof(T) == 8 ? P.tw64[2] : P.tw32[2]);
-    dim3 grid(P.nslab, nbands), block(256);
+    dim3 grid(P.nslab, nbands), block(kYzThreads);
     if (inverse) {
         static bool once = false;
         if (!once) {
@@ -155,19 +178,27 @@ static int launch_yz(bool inverse, const Plan &P, const KTables &K, const void *
     return check_launch("yz_fwd");
 }
 
+// j3 tile width of the x pass: the widest divisor of N3 in [8, 32], else 32 with a ragged last tile.
+static int xpass_tile(int n3) {
+    for (int t = kMaxT3; t >= 8; --t)
+        if (n3 % t == 0) return t;
+    return n3 < kMaxT3 ? n3 : kMaxT3;
+}
+
 template <int N1, typename T>
 static int launch_x(const Plan &P, const void *vloc, void *slab, int nbands, hipStream_t st) {
-    const size_t lds = (size_t)(N1 * P.N3 + N1) * sizeof(cx<T>);
-    if (lds > kLdsLimit) return set_error(ABACUS_PW_EBAD_FFT_SIZE, "x-z tile does not fit in LDS at this precision");
-    static size_t allowed = 0;
-    if (lds > allowed) {
+    const int T3 = xpass_tile(P.N3), nt3 = ceil_div(P.N3, T3);
+    const size_t lds = (size_t)(N1 * T3 + N1) * sizeof(cx<T>);
+    static bool once = false;
+    if (!once) {
         APW_TRY(allow_lds(k_xpass<N1, T, T>, kLdsLimit));
-        allowed = kLdsLimit;
+        once = true;
     }
     const cx<T> *tw = static_cast<const cx<T> *>(sizeof(T) == 8 ? P.tw64[0] : P.tw32[0]);
+    dim3 grid(P.N2 * nt3, ceil_div(nbands, kXBands));
     KernelTimer kt("xpass", st);
-    hipLaunchKernelGGL((k_xpass<N1, T, T>), dim3(P.N2, nbands), dim3(256), lds, st, static_cast<cx<T> *>(slab),
-                       P.nslab, P.N2, P.N3, P.row_to_slab, static_cast<const T *>(vloc), tw);
+    hipLaunchKernelGGL((k_xpass<N1, T, T>), grid, dim3(256), lds, st, static_cast<cx<T> *>(slab), P.nslab, P.N2,
+                       P.N3, T3, nt3, nbands, kXBands, P.row_to_slab, static_cast<const T *>(vloc), tw);
     return check_launch("xpass");
 }
 
@@ -216,7 +247,7 @@ int local_supported(const Plan &P, int fft_prec) {
         return set_error(ABACUS_PW_EBAD_FFT_SIZE, "grid length without a transform");
     if (P.N2 != P.N3) return set_error(ABACUS_PW_EBAD_FFT_SIZE, "the plane transform needs N2 == N3");
     const size_t cb = fft_prec == 0 ? 16 : 8;
-    if ((size_t)(P.N3 * P.N3 + P.N3) * cb > kLdsLimit || (size_t)(P.N1 * P.N3 + P.N1) * cb > kLdsLimit)
+    if ((size_t)(P.N3 * P.N3 + P.N3) * cb > kLdsLimit)
         return set_error(ABACUS_PW_EBAD_FFT_SIZE, "grid plane too large for LDS at this precision");
     return ABACUS_PW_OK;
 }
