@@ -1,0 +1,254 @@
+// Block Davidson driver (abacus_pw_davidson). Sec. III.B names Davidson as
+// the plane-wave eigensolver without listing its steps; the steps here are:
+//
+//  1. Cholesky-QR of the initial block X; W = H X; Rayleigh-Ritz on span(X).
+//  2. Repeat: residuals R = W - X Lambda and their FP64 norms; stop when every
+//     norm < tol. Teter-Payne-Allan preconditioned corrections for the
+//     unconverged bands, two classical Gram-Schmidt passes against the basis,
+//     corrections whose norm fell below 1e-10 of their pre-projection norm are
+//     dropped, Cholesky-QR twice; append T and H T to the basis; Rayleigh-Ritz
+//     on the whole basis keeping the lowest nb. When the basis would exceed
+//     ndim * nb vectors it restarts from the current Ritz vectors.
+//
+// Every vector operation runs on the device: GEMMs on MFMA, Cholesky and the
+// Hermitian eigensolver in FP64 (dense.hip). The host only reads the residual
+// norms (and the Cholesky status) once per iteration to steer the loop.
+//
+// Mixed modes: a first Davidson phase applies H in reduced precision (FP32
+// transforms and FP32 projector GEMMs, complex128 vectors), then an FP64
+// phase refines the Ritz vectors to tol with the FP64 H.
+#include <algorithm>
+#include <cmath>
+#include <vector>
+
+#include "davidson_kernels.hpp"
+#include "dense.hpp"
+#include "gemm.hpp"
+#include "hamiltonian.hpp"
+#include "local.hpp"
+
+namespace apw {
+
+namespace {
+
+struct Buffers {
+    DeviceBuffer V, HV, Xc, Wc, R, Y, Hs, Hw, coef, C, G, Linv, part, theta, rn2, ek, n0, n1, act, info, heev;
+};
+
+int d2h(void *dst, const void *src, size_t bytes, hipStream_t st) {
+    APW_HIP(hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToHost, st));
+    APW_HIP(hipStreamSynchronize(st));
+    return ABACUS_PW_OK;
+}
+
+int h2d(void *dst, const void *src, size_t bytes, hipStream_t st) {
+    APW_HIP(hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, st));
+    APW_HIP(hipStreamSynchronize(st));   // the host array may change right after
+    return ABACUS_PW_OK;
+}
+
+int d2d(void *dst, const void *src, size_t bytes, hipStream_t st) {
+    APW_HIP(hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToDevice, st));
+    return ABACUS_PW_OK;
+}
+
+// Orthonormalise the m rows of T (length npw) by `passes` Cholesky-QR passes;
+// Y is scratch of the same size. A Gram matrix that is not numerically
+// positive definite is retried once with the shift of shifted Cholesky-QR.
+int cholqr_rows(int m, int npw, z64 *T, z64 *Y, Buffers &b, int passes, hipStream_t st) {
+    z64 *G = b.G.as<z64>(), *Linv = b.Linv.as<z64>();
+    for (int pass = 0; pass < passes; ++pass) {
+        APW_TRY(gemm_cn(0, m, m, npw, T, npw, T, npw, G, m, 1.0, 0.0, b.part.ptr, 0, st));
+        APW_TRY(potrf_inv(m, G, m, Linv, m, b.info.as<int>(), st));
+        int info = 0;
+        APW_TRY(d2h(&info, b.info.ptr, sizeof(int), st));
+        if (info != 0) {
+            std::vector<double> nrm(m);
+            APW_TRY(dav_row_norm2(m, npw, T, b.n1.as<double>(), st));
+            APW_TRY(d2h(nrm.data(), b.n1.ptr, sizeof(double) * m, st));
+            double tr = 0.0;
+            for (double x : nrm) tr += x;
+            const double shift = 11.0 * ((double)m * npw + (double)m * (m + 1)) * 2.220446049250313e-16 * tr;
+            APW_TRY(gemm_cn(0, m, m, npw, T, npw, T, npw, G, m, 1.0, 0.0, b.part.ptr, 0, st));
+            APW_TRY(dav_add_diag(m, G, m, shift, st));
+            APW_TRY(potrf_inv(m, G, m, Linv, m, b.info.as<int>(), st));
+            APW_TRY(d2h(&info, b.info.ptr, sizeof(int), st));
+            if (info != 0) return set_error(ABACUS_PW_ECHOLESKY, "Gram matrix is not positive definite");
+            ++passes;   // a shifted pass is followed by one more plain pass
+            if (passes > 4) passes = 4;
+        }
+        APW_TRY(gemm_nn(0, m, npw, m, Linv, m, T, npw, Y, npw, 1.0, 0.0, st));
+        APW_TRY(d2d(T, Y, sizeof(z64) * (size_t)m * npw, st));
+    }
+    return ABACUS_PW_OK;
+}
+
+struct Result {
+    int iters = 0;
+    bool converged = false;
+};
+
+// One Davidson phase at k-point k on the [nb][npw] block X (in/out).
+// hprec: precision of H. stagnation > 0 stops the phase early when the largest
+// residual has not dropped below 0.7 of its best value for that many iterations.
+int davidson_k(const abacus_pw_problem &p, Plan &P, int k, int hprec, int nb, z64 *X, Buffers &b, double tol,
+               int max_iter, int ndim, int stagnation, std::vector<double> &theta_h, std::vector<double> &rn_h,
+               Result &res, hipStream_t st) {
+    const int npw = P.k[k].npw, nmax = ndim * nb;
+    const double *kin = P.k[k].kin;
+    if (nmax > kMaxSub) return set_error(ABACUS_PW_EBAD_SHAPE, "ndim * nb exceeds the device eigensolver limit (1024)");
+    const size_t vb = sizeof(z64) * (size_t)npw;
+    APW_TRY(b.V.ensure(vb * nmax));
+    APW_TRY(b.HV.ensure(vb * nmax));
+    APW_TRY(b.Xc.ensure(vb * nb));
+    APW_TRY(b.Wc.ensure(vb * nb));
+    APW_TRY(b.R.ensure(vb * nb));
+    APW_TRY(b.Y.ensure(vb * nb));
+    APW_TRY(b.Hs.ensure(sizeof(z64) * (size_t)nmax * nmax));
+    APW_TRY(b.Hw.ensure(sizeof(z64) * (size_t)nmax * nmax));
+    APW_TRY(b.coef.ensure(sizeof(z64) * (size_t)nb * nmax));
+    APW_TRY(b.C.ensure(sizeof(z64) * (size_t)nmax * nb));
+    APW_TRY(b.G.ensure(sizeof(z64) * (size_t)nb * nb));
+    APW_TRY(b.Linv.ensure(sizeof(z64) * (size_t)nb * nb));
+    APW_TRY(b.part.ensure(std::max(gemm_cn_part_bytes(nmax, nb, npw, 16, 0), gemm_cn_part_bytes(nb, nb, npw, 16, 0))));
+    APW_TRY(b.theta.ensure(sizeof(double) * nmax));
+    APW_TRY(b.rn2.ensure(sizeof(double) * nb));
+    APW_TRY(b.ek.ensure(sizeof(double) * nb));
+    APW_TRY(b.n0.ensure(sizeof(double) * nb));
+    APW_TRY(b.n1.ensure(sizeof(double) * nb));
+    APW_TRY(b.act.ensure(sizeof(int) * nb));
+    APW_TRY(b.info.ensure(sizeof(int)));
+    APW_TRY(b.heev.ensure(heev_scratch_bytes(nmax)));
+    z64 *V = b.V.as<z64>(), *HV = b.HV.as<z64>(), *Xc = b.Xc.as<z64>(), *Wc = b.Wc.as<z64>(), *R = b.R.as<z64>();
+    z64 *Y = b.Y.as<z64>(), *Hs = b.Hs.as<z64>(), *Hw = b.Hw.as<z64>(), *coef = b.coef.as<z64>(), *C = b.C.as<z64>();
+    double *theta = b.theta.as<double>();
+
+    // 1. Cholesky-QR, H X, Rayleigh-Ritz on span(X)
+    APW_TRY(d2d(Xc, X, vb * nb, st));
+    APW_TRY(cholqr_rows(nb, npw, Xc, Y, b, 1, st));
+    APW_TRY(apply_h_k(p, P, k, hprec, nb, Xc, Wc, st, false));
+    APW_TRY(gemm_cn(0, nb, nb, npw, Xc, npw, Wc, npw, C, nb, 1.0, 0.0, b.part.ptr, 0, st));
+    APW_TRY(dav_hs_append(0, nb, C, nb, Hs, nmax, st));
+    APW_TRY(dav_copy_block(nb, Hs, nmax, Hw, nmax, st));
+    APW_TRY(heev_lowest(nb, Hw, nmax, nb, theta, coef, nmax, b.heev.ptr, st));
+    APW_TRY(gemm_nn(0, nb, npw, nb, coef, nmax, Xc, npw, V, npw, 1.0, 0.0, st));
+    APW_TRY(gemm_nn(0, nb, npw, nb, coef, nmax, Wc, npw, HV, npw, 1.0, 0.0, st));
+    APW_TRY(d2d(Xc, V, vb * nb, st));
+    APW_TRY(d2d(Wc, HV, vb * nb, st));
+    APW_TRY(dav_hs_diag(nb, theta, Hs, nmax, st));
+    int nbasis = nb;
+
+    std::vector<double> rn2(nb), n0(nb), n1(nb);
+    std::vector<int> act, keep;
+    double best = INFINITY;
+    int since_best = 0;
+    res = Result{};
+    for (;;) {
+        APW_TRY(dav_resid(nb, npw, Xc, Wc, theta, kin, R, b.rn2.as<double>(), b.ek.as<double>(), st));
+        APW_TRY(d2h(rn2.data(), b.rn2.ptr, sizeof(double) * nb, st));
+        act.clear();
+        double worst = 0.0;
+        for (int n = 0; n < nb; ++n) {
+            const double r = std::sqrt(rn2[n]);
+            worst = std::max(worst, r);
+            if (!(r < tol)) act.push_back(n);
+        }
+        if (act.empty()) {
+            res.converged = true;
+            break;
+        }
+        if (res.iters >= max_iter) break;
+        if (stagnation > 0) {
+            if (worst < 0.7 * best) {
+                best = worst;
+                since_best = 0;
+            } else if (++since_best >= stagnation) {
+                break;
+            }
+        }
+        int m = (int)act.size();
+        APW_TRY(h2d(b.act.ptr, act.data(), sizeof(int) * m, st));
+        if (nbasis + m > nmax) {
+            APW_TRY(d2d(V, Xc, vb * nb, st));
+            APW_TRY(d2d(HV, Wc, vb * nb, st));
+            APW_TRY(dav_hs_diag(nb, theta, Hs, nmax, st));
+            nbasis = nb;
+        }
+        z64 *T = V + (size_t)nbasis * npw, *HT = HV + (size_t)nbasis * npw;
+        APW_TRY(dav_precond(m, npw, b.act.as<int>(), R, kin, b.ek.as<double>(), T, st));
+        APW_TRY(dav_row_norm2(m, npw, T, b.n0.as<double>(), st));
+        for (int pass = 0; pass < 2; ++pass) {
+            APW_TRY(gemm_cn(0, nbasis, m, npw, V, npw, T, npw, C, nbasis, 1.0, 0.0, b.part.ptr, 0, st));
+            APW_TRY(gemm_nn(0, m, npw, nbasis, C, nbasis, V, npw, T, npw, -1.0, 1.0, st));
+        }
+        APW_TRY(dav_row_norm2(m, npw, T, b.n1.as<double>(), st));
+        APW_TRY(d2h(n0.data(), b.n0.ptr, sizeof(double) * m, st));
+        APW_TRY(d2h(n1.data(), b.n1.ptr, sizeof(double) * m, st));
+        keep.clear();
+        for (int i = 0; i < m; ++i)
+            if (std::sqrt(n1[i]) >= 1e-10 * std::sqrt(n0[i])) keep.push_back(i);
+        if ((int)keep.size() < m) {
+            if (!keep.empty()) {
+                APW_TRY(h2d(b.act.ptr, keep.data(), sizeof(int) * keep.size(), st));
+                APW_TRY(dav_gather_rows((int)keep.size(), npw, b.act.as<int>(), T, Y, st));
+                APW_TRY(d2d(T, Y, vb * keep.size(), st));
+            }
+            m = (int)keep.size();
+        }
+        if (m == 0) break;
+        APW_TRY(cholqr_rows(m, npw, T, Y, b, 2, st));
+        APW_TRY(apply_h_k(p, P, k, hprec, m, T, HT, st, false));
+        const int n = nbasis + m;
+        APW_TRY(gemm_cn(0, n, m, npw, V, npw, HT, npw, C, n, 1.0, 0.0, b.part.ptr, 0, st));
+        APW_TRY(dav_hs_append(nbasis, m, C, n, Hs, nmax, st));
+        APW_TRY(dav_copy_block(n, Hs, nmax, Hw, nmax, st));
+        APW_TRY(heev_lowest(n, Hw, nmax, nb, theta, coef, nmax, b.heev.ptr, st));
+        APW_TRY(gemm_nn(0, nb, npw, n, coef, nmax, V, npw, Xc, npw, 1.0, 0.0, st));
+        APW_TRY(gemm_nn(0, nb, npw, n, coef, nmax, HV, npw, Wc, npw, 1.0, 0.0, st));
+        nbasis = n;
+        ++res.iters;
+    }
+    APW_TRY(d2d(X, Xc, vb * nb, st));
+    theta_h.assign(nb, 0.0);
+    APW_TRY(d2h(theta_h.data(), theta, sizeof(double) * nb, st));
+    rn_h.resize(nb);
+    for (int n = 0; n < nb; ++n) rn_h[n] = std::sqrt(rn2[n]);
+    return ABACUS_PW_OK;
+}
+
+}  // namespace
+
+int davidson_all(const abacus_pw_problem &p, Plan &P, int prec, int nb, void *psi, double *eig, double tol,
+                 int max_iter, int ndim, int *iters, double *resid, hipStream_t st) {
+    if (prec == ABACUS_PW_MIXED_BF16)
+        return set_error(ABACUS_PW_EBAD_PRECISION, "MIXED_BF16 Davidson is not offered by this build");
+    APW_TRY(local_supported(P, 0));   // the refinement phase always runs FP64 transforms
+    Buffers b;
+    bool all = true;
+    std::vector<double> th, rn;
+    // operator copies once per solve (the reduced-precision phase reads them)
+    APW_TRY(operator_copies(p, P, prec != ABACUS_PW_FP64, prec != ABACUS_PW_FP64, st));
+    for (int k = 0; k < P.nk; ++k) {
+        z64 *X = static_cast<z64 *>(psi) + (size_t)nb * P.k[k].pw_off;
+        int total = 0;
+        Result r;
+        if (prec == ABACUS_PW_MIXED_FP32) {
+            APW_TRY(davidson_k(p, P, k, ABACUS_PW_MIXED_FP32, nb, X, b, std::max(tol, 1e-5), max_iter, ndim, 3, th, rn,
+                               r, st));
+            total += r.iters;
+        }
+        APW_TRY(davidson_k(p, P, k, ABACUS_PW_FP64, nb, X, b, tol, std::max(0, max_iter - total), ndim, 0, th, rn, r,
+                           st));
+        total += r.iters;
+        all = all && r.converged;
+        for (int n = 0; n < nb; ++n) {
+            eig[(size_t)k * nb + n] = th[n];
+            if (resid) resid[(size_t)k * nb + n] = rn[n];
+        }
+        if (iters) iters[k] = total;
+    }
+    APW_HIP(hipStreamSynchronize(st));
+    return all ? ABACUS_PW_OK : ABACUS_PW_NOT_CONVERGED;
+}
+
+}  // namespace apw

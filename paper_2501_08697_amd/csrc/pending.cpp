@@ -8,9 +8,4 @@ int apply_h_backward_all(const abacus_pw_problem &, Plan &, int, int, const void
     return set_error(ABACUS_PW_EINTERNAL, "adjoint not available in this build");
 }
 
-int davidson_all(const abacus_pw_problem &, Plan &, int, int, void *, double *, double, int, int, int *, double *,
-                 hipStream_t) {
-    return set_error(ABACUS_PW_EINTERNAL, "Davidson not available in this build");
-}
-
 }  // namespace apw

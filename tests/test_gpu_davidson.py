@@ -1,0 +1,152 @@
+"""GPU block Davidson (abacus_pw_davidson) against the FP64 oracle.
+
+Eigenvectors are unique only up to rotations inside degenerate clusters, so
+the checks compare eigenvalues, residual norms recomputed by the oracle's
+H psi on the GPU's vectors, Rayleigh quotients and orthonormality.
+"""
+import dataclasses
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2501_08697_amd import workload as W
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+def B():
+    from paper_2501_08697_amd import binding
+    return binding
+
+
+def gpu_davidson(prob, tol, max_iter, ndim=2, prec=0, nb=None, psi0=None):
+    b = B()
+    nb = prob.nb if nb is None else nb
+    print(f"[davidson] {prob.name} fft={prob.fft} npw={list(prob.npw)} nb={nb} tol={tol} prec={prec}", flush=True)
+    dp = b.DeviceProblem(prob)
+    x0 = prob.psi if psi0 is None else psi0
+    x = torch.from_numpy(np.ascontiguousarray(x0)).cuda()
+    eig, res, its, st = b.davidson(dp, x, tol=tol, max_iter=max_iter, ndim=ndim, precision=prec, nb=nb)
+    return eig, x.cpu().numpy(), res, its, st
+
+
+def check_vectors(prob, psi, eig, nb, rtol):
+    """Oracle residuals, Rayleigh quotients and orthonormality of the GPU's Ritz pairs."""
+    off = prob.pw_offsets
+    for k in range(prob.nk):
+        sub = oracle._single_k(prob, k)
+        x = psi[nb * off[k]: nb * off[k + 1]].reshape(nb, -1)
+        hx = oracle.apply_h(sub, x.reshape(-1), nb=nb).reshape(nb, -1)
+        assert np.max(np.abs(x.conj() @ x.T - np.eye(nb))) < 1e-12
+        rq = np.real(np.sum(x.conj() * hx, axis=1))
+        assert np.max(np.abs(rq - eig[k])) < 1e-10 * max(1.0, np.max(np.abs(eig[k])))
+        r = np.linalg.norm(hx - eig[k][:, None] * x, axis=1)
+        assert np.max(r) < rtol, np.max(r)
+
+
+def test_tiny_matches_dense():
+    p = W.make_problem(W.tiny_config(fft=16, ecut=14.0, nb=6, kfrac=((0.1, 0.0, 0.2),), lmax=2, natom=2))
+    ev = np.linalg.eigvalsh(oracle.dense_h(p, 0))[:6]
+    eig, psi, res, its, st = gpu_davidson(p, 1e-11, 300)
+    assert st == 0 and np.max(res) < 1e-11
+    np.testing.assert_allclose(eig[0], ev, atol=1e-12)
+    check_vectors(p, psi, eig, p.nb, 2e-11)
+
+
+def test_free_electron_degenerate_shells():
+    """V = 0, D = 0: eigenvalues are the sorted |k+G|^2 with exact degeneracies."""
+    p = W.make_problem(W.tiny_config(fft=16, ecut=14.0, nb=7))
+    q = dataclasses.replace(p, vloc=np.zeros_like(p.vloc), dmat=np.zeros_like(p.dmat))
+    kin = np.sort(oracle.kinetic(q, 0))
+    eig, psi, res, its, st = gpu_davidson(q, 1e-11, 200)
+    assert st == 0
+    np.testing.assert_allclose(eig[0], kin[:7], atol=1e-12)
+    check_vectors(q, psi, eig, q.nb, 2e-11)
+
+
+def test_c1_twenty_iterations_against_oracle():
+    p = W.make_problem("C1")
+    eig, psi, res, its, st = gpu_davidson(p, 1e-13, 20)
+    assert its[0] == 20 and st == 1
+    e_o, x_o, r_o, it_o = oracle.davidson(p, tol=1e-13, max_iter=20)
+    ev = np.linalg.eigvalsh(oracle.dense_h(p, 0))
+    good = (res[0] < 1e-9) & (r_o[0] < 1e-9)
+    assert np.sum(good) >= 7
+    np.testing.assert_allclose(eig[0][good], ev[:16][good], atol=1e-12)
+    # Unconverged bands: each GPU Ritz value lies within its Krylov-Weinstein bound r_n
+    # (and the Kato-Temple bound r_n^2 / gap) of a dense eigenvalue, and agrees with the
+    # oracle's run of the same iteration within max(r)^2 (both sit within ~r^2/gap of the
+    # same eigenvalue; rounding differences move an unconverged iterate at that scale).
+    lam, r = eig[0], res[0]
+    for n in range(p.nb):
+        j = np.argmin(np.abs(ev - lam[n]))
+        gap = np.min(np.abs(np.delete(ev, j) - lam[n]))
+        err = abs(lam[n] - ev[j])
+        assert err <= r[n] * (1 + 1e-9) + 1e-13
+        if gap > r[n]:
+            assert err <= r[n] ** 2 / (gap - r[n]) + 1e-13
+    assert np.all(np.abs(lam - e_o[0]) <= np.maximum(r, r_o[0]) ** 2 + 1e-12)
+    np.testing.assert_allclose(r, r_o[0], rtol=1e-2, atol=1e-12)
+
+
+def test_c1_converged_matches_dense():
+    p = W.make_problem("C1")
+    ev = np.linalg.eigvalsh(oracle.dense_h(p, 0))[:16]
+    eig, psi, res, its, st = gpu_davidson(p, 1e-10, 400)
+    assert st == 0 and np.max(res) < 1e-10
+    np.testing.assert_allclose(eig[0], ev, atol=1e-12)
+    check_vectors(p, psi, eig, 16, 1.5e-10)
+
+
+def test_two_kpoints_ndim3():
+    p = W.make_problem(W.tiny_config(fft=16, ecut=16.0, nb=5, kfrac=((0.0, 0.0, 0.0), (0.5, 0.25, 0.0)), natom=3))
+    eig, psi, res, its, st = gpu_davidson(p, 1e-10, 300, ndim=3)
+    assert st == 0
+    for k in range(p.nk):
+        ev = np.linalg.eigvalsh(oracle.dense_h(p, k))[:5]
+        np.testing.assert_allclose(eig[k], ev, atol=1e-11)
+    check_vectors(p, psi, eig, 5, 1.5e-10)
+
+
+def test_c2_small_block_against_oracle_davidson():
+    """C2 cell with 16 bands, both sides to a 1e-8 residual."""
+    p = W.make_problem("C2", nb=16)
+    eig, psi, res, its, st = gpu_davidson(p, 1e-8, 300)
+    assert st == 0
+    e_o, x_o, r_o, it_o = oracle.davidson(p, tol=1e-8, max_iter=300)
+    np.testing.assert_allclose(eig[0], e_o[0], atol=1e-10)
+    check_vectors(p, psi, eig, 16, 1.5e-8)
+
+
+def test_c2_full_to_1e8():
+    """The benchmark workload: 128 bands to a 1e-8 residual, verified by the oracle's H psi."""
+    p = W.make_problem("C2")
+    eig, psi, res, its, st = gpu_davidson(p, 1e-8, 300)
+    assert st == 0 and np.max(res) < 1e-8
+    assert np.all(np.diff(eig[0]) >= -1e-12)
+    check_vectors(p, psi, eig, 128, 1.5e-8)
+
+
+def test_mixed_fp32_refines_to_fp64():
+    p = W.make_problem("C1")
+    e64, _, _, _, st64 = gpu_davidson(p, 1e-10, 400)
+    emx, psi, res, its, st = gpu_davidson(p, 1e-10, 400, prec=B().MIXED_FP32)
+    assert st == 0 and st64 == 0
+    np.testing.assert_allclose(emx, e64, atol=1e-11)
+    check_vectors(p, psi, emx, 16, 1.5e-10)
+
+
+def test_rejects_bad_sizes():
+    b = B()
+    p = W.make_problem(W.tiny_config(fft=8, ecut=5.0, nb=2))
+    dp = b.DeviceProblem(p)
+    x = torch.from_numpy(np.zeros(p.npw[0] * (int(p.npw[0]) + 1), dtype=np.complex128)).cuda()
+    with pytest.raises(b.AbacusPwError) as e:
+        b.davidson(dp, x, nb=int(p.npw[0]) + 1)
+    assert e.value.name == "EBAD_SHAPE"
+    x = torch.from_numpy(p.psi).cuda()
+    with pytest.raises(b.AbacusPwError) as e:
+        b.davidson(dp, x, ndim=1)
+    assert e.value.name == "EBAD_SHAPE"
