@@ -241,6 +241,25 @@ __global__ __launch_bounds__(256) void k_gemm_nn(int M, int G, int K, const cx<T
         }
 }
 
+// grad_d[blk(i)][i - lo][t] (+)= sum_n Re(Q[n][i] conj(P[n][lo + t])), one thread per projector i.
+template <typename T>
+__global__ void k_grad_d(int nb, int M, const cx<T> *__restrict__ P, const cx<T> *__restrict__ Q,
+                         const int *__restrict__ blo, const int *__restrict__ bn, const int *__restrict__ bdoff,
+                         double *__restrict__ gd, int first) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= M) return;
+    const int lo = blo[i], n = bn[i];
+    double *out = gd + bdoff[i] + (int64_t)(i - lo) * n;
+    for (int t = 0; t < n; ++t) {
+        double s = 0.0;
+        for (int b = 0; b < nb; ++b) {
+            const cx<T> q = Q[(int64_t)b * M + i], p = P[(int64_t)b * M + lo + t];
+            s += (double)q.re * (double)p.re + (double)q.im * (double)p.im;
+        }
+        out[t] = first ? s : out[t] + s;
+    }
+}
+
 // ------------------------------------------------------------ launchers ----
 static int splits_for(int M, int N, int K, int chunk_hint, int *chunk) {
     const int tiles = ceil_div(M, TM) * ceil_div(N, TN);
@@ -339,6 +358,18 @@ int gemm_nn(int prec, int M, int G, int K, const void *A, int64_t lda, const voi
 int gemm_nn_f32_into_f64(int M, int G, int K, const void *A, int64_t lda, const void *B, int64_t ldb, void *C,
                          int64_t ldc, double alpha, double beta, hipStream_t st) {
     return gemm_nn_t<float, double>(M, G, K, A, lda, B, ldb, C, ldc, alpha, beta, st);
+}
+
+int grad_d_accumulate(int prec, int nb, int M, const void *P, const void *Q, const int *blo, const int *bn,
+                      const int *bdoff, double *gd, int first, hipStream_t st) {
+    KernelTimer kt("grad_d", st);
+    if (prec == 0)
+        hipLaunchKernelGGL(k_grad_d<double>, dim3(ceil_div(M, 64)), dim3(64), 0, st, nb, M,
+                           static_cast<const z64 *>(P), static_cast<const z64 *>(Q), blo, bn, bdoff, gd, first);
+    else
+        hipLaunchKernelGGL(k_grad_d<float>, dim3(ceil_div(M, 64)), dim3(64), 0, st, nb, M,
+                           static_cast<const c32 *>(P), static_cast<const c32 *>(Q), blo, bn, bdoff, gd, first);
+    return check_launch("grad_d");
 }
 
 }  // namespace apw

@@ -26,4 +26,8 @@ int gemm_nn(int prec, int M, int G, int K, const void *A, int64_t lda, const voi
 int gemm_nn_f32_into_f64(int M, int G, int K, const void *A, int64_t lda, const void *B, int64_t ldb, void *C,
                          int64_t ldc, double alpha, double beta, hipStream_t st);
 
+// grad_d entry (i, lo+t) of each atom block (+)= sum_n Re(Q[n][i] conj(P[n][lo+t])); P, Q are [nb][M].
+int grad_d_accumulate(int prec, int nb, int M, const void *P, const void *Q, const int *blo, const int *bn,
+                      const int *bdoff, double *gd, int first, hipStream_t st);
+
 }  // namespace apw

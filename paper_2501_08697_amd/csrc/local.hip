@@ -137,6 +137,75 @@ __global__ __launch_bounds__(kYzThreads) void k_yz_fwd(const cx<T> *__restrict__
     }
 }
 
+// Adjoint of the local term with respect to V: for one (j2, j3 tile) and the
+// bands b = g, g + G, ... of the batch, inverse x transforms of the psi and dY
+// planes and acc(r) += Re(conj(gamma_b(r)) psi_b(r)); part[g] holds the running
+// sum (overwritten when first != 0). Bands are summed in a fixed order.
+template <int N1, typename T>
+__global__ __launch_bounds__(256) void k_gradv_x(const cx<T> *__restrict__ slab_x, const cx<T> *__restrict__ slab_y,
+                                                 int nslab, int N2, int N3, int T3, int nt3, int nbands, int G,
+                                                 const int *__restrict__ row_to_slab, const cx<T> *__restrict__ tw_g,
+                                                 double *__restrict__ part, int first) {
+    constexpr int MAXV = (N1 * kMaxT3 + 255) / 256;
+    extern __shared__ __align__(16) unsigned char smem[];
+    cx<T> *tile = reinterpret_cast<cx<T> *>(smem);
+    cx<T> *tw = tile + N1 * T3;
+    const int j2 = blockIdx.x / nt3, c0 = (blockIdx.x - j2 * nt3) * T3;
+    const int w3 = min(T3, N3 - c0);
+    const int g = blockIdx.y;
+    const int tid = threadIdx.x, nthr = blockDim.x;
+    const int64_t plane = (int64_t)N2 * N3;
+    const int ntile = N1 * w3;
+    for (int i = tid; i < N1; i += nthr) tw[i] = tw_g[i];
+    double acc[MAXV];
+    cx<T> xr[MAXV];
+#pragma unroll
+    for (int q = 0; q < MAXV; ++q) acc[q] = 0.0;
+    for (int b = g; b < nbands; b += G) {
+        for (int src = 0; src < 2; ++src) {
+            const cx<T> *base = (src == 0 ? slab_x : slab_y) + (int64_t)b * nslab * plane + (int64_t)j2 * N3 + c0;
+            for (int i = tid; i < ntile; i += nthr) {
+                const int r = i / w3, c = i - r * w3;
+                const int s = row_to_slab[r];
+                tile[i] = s >= 0 ? base[s * plane + c] : czero<T>();
+            }
+            __syncthreads();
+            lds_fft<N1, +1, true>(tile, w3, [](int l) { return l; }, w3, tw);
+#pragma unroll
+            for (int q = 0; q < MAXV; ++q) {
+                const int i = tid + q * 256;
+                if (i < ntile) {
+                    if (src == 0) {
+                        xr[q] = tile[i];
+                    } else {
+                        const cx<T> y = tile[i];
+                        acc[q] += (double)y.re * (double)xr[q].re + (double)y.im * (double)xr[q].im;
+                    }
+                }
+            }
+            __syncthreads();
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < MAXV; ++q) {
+        const int i = tid + q * 256;
+        if (i < ntile) {
+            const int r = i / w3, c = i - r * w3;
+            double *o = part + (int64_t)g * N1 * plane + (int64_t)r * plane + (int64_t)j2 * N3 + c0 + c;
+            *o = first ? acc[q] : *o + acc[q];
+        }
+    }
+}
+
+// grad_v[j] = (1/N) sum_{g < G} part[g][j]   (fixed order)
+__global__ void k_gradv_reduce(int64_t n, int G, const double *__restrict__ part, double *__restrict__ out, double inv_n) {
+    for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < n; j += (int64_t)gridDim.x * blockDim.x) {
+        double s = 0.0;
+        for (int g = 0; g < G; ++g) s += part[(int64_t)g * n + j];
+        out[j] = s * inv_n;
+    }
+}
+
 // ------------------------------------------------------------ launchers ----
 template <typename K> static int allow_lds(K kernel, size_t bytes) {
     APW_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(kernel),
@@ -254,6 +323,55 @@ int local_supported(const Plan &P, int fft_prec) {
 
 size_t local_slab_bytes(const Plan &P, int fft_prec, int nbands) {
     return (size_t)nbands * (size_t)P.nslab * (size_t)P.N2 * (size_t)P.N3 * (fft_prec == 0 ? 16 : 8);
+}
+
+
+template <int N1, typename T>
+static int launch_gradv(const Plan &P, const void *sx, const void *sy, int nbands, double *part, int G, int first,
+                        hipStream_t st) {
+    const int T3 = xpass_tile(P.N3), nt3 = ceil_div(P.N3, T3);
+    const size_t lds = (size_t)(N1 * T3 + N1) * sizeof(cx<T>);
+    static bool once = false;
+    if (!once) {
+        APW_TRY(allow_lds(k_gradv_x<N1, T>, kLdsLimit));
+        once = true;
+    }
+    const cx<T> *tw = static_cast<const cx<T> *>(sizeof(T) == 8 ? P.tw64[0] : P.tw32[0]);
+    KernelTimer kt("gradv_x", st);
+    hipLaunchKernelGGL((k_gradv_x<N1, T>), dim3(P.N2 * nt3, G), dim3(256), lds, st, static_cast<const cx<T> *>(sx),
+                       static_cast<const cx<T> *>(sy), P.nslab, P.N2, P.N3, T3, nt3, nbands, G, P.row_to_slab, tw,
+                       part, first);
+    return check_launch("gradv_x");
+}
+
+int local_inverse_planes(const Plan &P, int kidx, int fft_prec, int io_prec, const void *psi, void *slab, int nbands,
+                         hipStream_t st) {
+    const KTables &K = P.k[kidx];
+    if (fft_prec == 0) return dispatch_yz<double, double>(true, P, K, psi, nullptr, slab, nbands, st);
+    if (io_prec == 1) return dispatch_yz<float, float>(true, P, K, psi, nullptr, slab, nbands, st);
+    return dispatch_yz<float, double>(true, P, K, psi, nullptr, slab, nbands, st);
+}
+
+int local_gradv_accumulate(const Plan &P, int fft_prec, const void *slab_x, const void *slab_y, int nbands,
+                           double *part, int G, int first, hipStream_t st) {
+    switch (P.N1) {
+#define APW_CASE(n)                                                                                     \
+    case n:                                                                                             \
+        return fft_prec == 0 ? launch_gradv<n, double>(P, slab_x, slab_y, nbands, part, G, first, st) \
+                             : launch_gradv<n, float>(P, slab_x, slab_y, nbands, part, G, first, st);
+        APW_LENGTHS(APW_CASE)
+#undef APW_CASE
+        default:
+            return set_error(ABACUS_PW_EBAD_FFT_SIZE, "unsupported grid length");
+    }
+}
+
+int local_gradv_finish(const Plan &P, const double *part, int G, double *grad_v, hipStream_t st) {
+    KernelTimer kt("gradv_reduce", st);
+    const int64_t blocks = std::min<int64_t>(ceil_div64(P.N, 256), 8192);
+    hipLaunchKernelGGL(k_gradv_reduce, dim3((unsigned)blocks), dim3(256), 0, st, (int64_t)P.N, G, part, grad_v,
+                       1.0 / (double)P.N);
+    return check_launch("gradv_reduce");
 }
 
 int local_term(const Plan &P, int kidx, int fft_prec, int io_prec, const void *vloc, const void *psi, void *hpsi,

@@ -18,4 +18,14 @@ size_t local_slab_bytes(const Plan &P, int fft_prec, int nbands);
 int local_term(const Plan &P, int kidx, int fft_prec, int io_prec, const void *vloc, const void *psi, void *hpsi,
                int nb, void *slab, int band_batch, hipStream_t st);
 
+// Inverse y-z transforms of nbands bands of k-point kidx into slab planes (first pass of local_term).
+int local_inverse_planes(const Plan &P, int kidx, int fft_prec, int io_prec, const void *psi, void *slab, int nbands,
+                         hipStream_t st);
+// part[g] (+)= sum over bands b = g (mod G) of Re(conj(gamma_b(r)) psi_b(r)), from the slab planes of
+// psi (slab_x) and dY (slab_y); part is [G][N1][N2][N3]; first != 0 overwrites.
+int local_gradv_accumulate(const Plan &P, int fft_prec, const void *slab_x, const void *slab_y, int nbands,
+                           double *part, int G, int first, hipStream_t st);
+// grad_v = (1/N) sum_g part[g]
+int local_gradv_finish(const Plan &P, const double *part, int G, double *grad_v, hipStream_t st);
+
 }  // namespace apw

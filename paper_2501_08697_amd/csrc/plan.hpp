@@ -74,6 +74,7 @@ struct Plan {
 
     // work space
     DeviceBuffer slab;        // [band_batch][nslab][N2][N3] complex
+    DeviceBuffer slab2;       // second slab (adjoint: planes of dY)
     DeviceBuffer gemm_part;   // split-K partial sums
     DeviceBuffer proj;        // P = B^H psi  [nb][nproj] complex128 (or complex64)
     DeviceBuffer projq;       // Q = D P

@@ -1,0 +1,160 @@
+"""GPU adjoint (abacus_pw_apply_h_backward) against the FP64 oracle, central
+finite differences of the GPU forward, closed forms, and the autograd wrapper.
+
+FP64 bar: 1e-12 relative max-norm per gradient. FP32 bar: 1e-5 (as for H psi).
+Finite differences: L = Re <dY, H psi> is linear in psi, V and D, so a central
+difference with h = 1e-6 is exact up to rounding of L (|L| eps / h ~ 1e-10 of
+|dL|); the bar is 1e-7 relative.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2501_08697_amd import workload as W
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+def B():
+    from paper_2501_08697_amd import binding
+    return binding
+
+
+def rel(a, b):
+    return float(np.max(np.abs(a - b)) / np.max(np.abs(b)))
+
+
+def gpu_backward(prob, psi, dy, nb, prec=0, dp=None):
+    b = B()
+    print(f"[backward] {prob.name} fft={prob.fft} nk={prob.nk} nb={nb} prec={prec}", flush=True)
+    dp = dp or b.DeviceProblem(prob)
+    x = torch.from_numpy(np.ascontiguousarray(psi)).cuda()
+    g = torch.from_numpy(np.ascontiguousarray(dy)).cuda()
+    if prec == b.FP32:
+        x, g = x.to(torch.complex64), g.to(torch.complex64)
+    gp, gv, gd = b.apply_h_backward(dp, x, g, prec, nb=nb)
+    torch.cuda.synchronize()
+    return gp.cpu().numpy().astype(np.complex128), gv.cpu().numpy(), gd.cpu().numpy()
+
+
+def subset(prob, arr, nsub):
+    """The first nsub bands of every k block of a packed band array."""
+    return np.concatenate([prob.psi_k(k, arr)[:nsub].reshape(-1) for k in range(prob.nk)])
+
+
+def sub_problem(prob, nsub):
+    import dataclasses
+    q = dataclasses.replace(prob)
+    q.nb = nsub
+    q.psi = subset(prob, prob.psi, nsub)
+    q.dy = subset(prob, prob.dy, nsub)
+    return q
+
+
+def tiny():
+    return W.make_problem(W.tiny_config(fft=16, ecut=16.0, nb=5, kfrac=((0.1, 0.2, -0.1), (0.5, 0.0, 0.0)), lmax=2,
+                                        dfull=True, natom=3, with_grad_inputs=True))
+
+
+def test_tiny_two_kpoints_fp64():
+    p = tiny()
+    gp, gv, gd = gpu_backward(p, p.psi, p.dy, p.nb)
+    rp, rv, rd = oracle.apply_h_backward(p, p.psi, p.dy)
+    assert rel(gp, rp) < 1e-12 and rel(gv, rv) < 1e-12 and rel(gd, rd) < 1e-12
+
+
+def test_c1_fp64():
+    p = W.make_problem(W.tiny_config(a=10.0, ecut=20.0, fft=32, natom=8, nb=16, seed=1, with_grad_inputs=True))
+    gp, gv, gd = gpu_backward(p, p.psi, p.dy, p.nb)
+    rp, rv, rd = oracle.apply_h_backward(p, p.psi, p.dy)
+    assert rel(gp, rp) < 1e-12 and rel(gv, rv) < 1e-12 and rel(gd, rd) < 1e-12
+
+
+def test_tiny_fp32():
+    p = tiny()
+    gp, gv, gd = gpu_backward(p, p.psi, p.dy, p.nb, prec=B().FP32)
+    rp, rv, rd = oracle.apply_h_backward(p, p.psi, p.dy)
+    assert rel(gp, rp) < 1e-5 and rel(gv, rv) < 1e-5 and rel(gd, rd) < 1e-5
+
+
+def test_repeat_bitwise():
+    p = tiny()
+    a = gpu_backward(p, p.psi, p.dy, p.nb)
+    b = gpu_backward(p, p.psi, p.dy, p.nb)
+    for x, y in zip(a, b):
+        assert np.array_equal(x, y)
+
+
+@pytest.fixture(scope="module")
+def c5():
+    return W.make_problem("C5")
+
+
+def test_c5_band_subset_against_oracle(c5):
+    """C5 geometry (96^3, four uneven k-points, 512 projectors), 8 bands per k."""
+    q = sub_problem(c5, 8)
+    gp, gv, gd = gpu_backward(q, q.psi, q.dy, 8)
+    rp, rv, rd = oracle.apply_h_backward(q, q.psi, q.dy)
+    assert rel(gp, rp) < 1e-12 and rel(gv, rv) < 1e-12 and rel(gd, rd) < 1e-12
+
+
+def test_c5_full_additivity_and_finite_differences(c5):
+    """All 256 bands per k: grad_V and grad_D equal the sum over four 64-band slices;
+    sampled grad_psi bands equal the oracle's H dY; central differences of the GPU forward."""
+    b = B()
+    p = c5
+    dp = b.DeviceProblem(p, static=False)
+    gp, gv, gd = gpu_backward(p, p.psi, p.dy, p.nb, dp=dp)
+    acc_v, acc_d = np.zeros_like(gv), np.zeros_like(gd)
+    for s in range(4):
+        sl = lambda arr: np.concatenate([p.psi_k(k, arr)[64 * s: 64 * (s + 1)].reshape(-1) for k in range(p.nk)])
+        _, v_s, d_s = gpu_backward(p, sl(p.psi), sl(p.dy), 64, dp=dp)
+        acc_v += v_s
+        acc_d += d_s
+    assert rel(acc_v, gv) < 1e-12 and rel(acc_d, gd) < 1e-12
+    take = [0, 255]
+    for k in range(p.nk):
+        sub = oracle._single_k(p, k)
+        ref = oracle.apply_h(sub, p.psi_k(k, p.dy)[take].reshape(-1), nb=len(take)).reshape(len(take), -1)
+        assert rel(p.psi_k(k, gp)[take], ref) < 1e-12
+    # central differences along random directions, forward on the GPU
+    rng = np.random.default_rng(5)
+    x = torch.from_numpy(p.psi).cuda()
+    g = torch.from_numpy(p.dy).cuda()
+    h = 1e-6
+
+    def loss(vloc=None, dmat=None):
+        y = b.apply_h(dp, x, vloc=vloc, dmat=dmat)
+        return float(torch.real(torch.vdot(g, y)).item())
+
+    dv = torch.from_numpy(rng.standard_normal(p.fft)).cuda()
+    fd = (loss(vloc=dp.vloc + h * dv) - loss(vloc=dp.vloc - h * dv)) / (2 * h)
+    an = float(np.sum(gv * dv.cpu().numpy()))
+    assert abs(fd - an) <= 1e-7 * abs(an)
+    dd = torch.from_numpy(rng.standard_normal(p.dmat.size)).cuda()
+    fd = (loss(dmat=dp.dmat + h * dd) - loss(dmat=dp.dmat - h * dd)) / (2 * h)
+    an = float(np.sum(gd * dd.cpu().numpy()))
+    assert abs(fd - an) <= 1e-7 * abs(an)
+
+
+def test_autograd_band_energy_closed_forms():
+    """L = sum_n f_n <psi_n|H psi_n>: dL/dpsi = 2 f H psi, dL/dV = density, dL/dD = Re f P P^H."""
+    from paper_2501_08697_amd import autograd
+    b = B()
+    p = W.make_problem(W.tiny_config(fft=16, ecut=16.0, nb=6, kfrac=((0.2, 0.0, 0.1),), natom=3,
+                                     with_grad_inputs=True))
+    dp = b.DeviceProblem(p, static=False)
+    x = torch.from_numpy(p.psi).cuda().requires_grad_(True)
+    v = dp.vloc.clone().requires_grad_(True)
+    d = dp.dmat.clone().requires_grad_(True)
+    f = torch.from_numpy(np.repeat(p.occ[0], p.npw[0])).cuda()
+    y = autograd.apply_h(dp, x, v, d)
+    loss = torch.real(torch.sum(f * torch.conj(x) * y))
+    loss.backward()
+    hx = oracle.apply_h(p, p.psi)
+    fn = np.repeat(p.occ[0], p.npw[0])
+    assert rel(x.grad.cpu().numpy(), 2 * fn * hx) < 1e-12
+    _, rv, rd = oracle.apply_h_backward(p, p.psi, fn * p.psi, want=("v", "d"))
+    assert rel(v.grad.cpu().numpy(), rv) < 1e-12
+    assert rel(d.grad.cpu().numpy(), rd) < 1e-12
