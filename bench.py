@@ -45,19 +45,21 @@ def parse():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-davidson", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true")
     return ap.parse_args()
 
 
-def kernel_model(name, prob, bb, nb):
+def kernel_model(name, prob, nb, launches):
     """Algorithmic (bytes, flops) of ONE launch of a library kernel at this workload.
 
-    cb = 16 bytes per complex128. S = nslab * N2 * N3 (the slab: grid planes that
-    hold sphere points), npw sphere points; a band-batch launch covers bb bands.
-      yz_inv : bb * cb * (npw + S)          read psi, write the slab planes
-      xpass  : bb * cb * 2 S + 8 N          slab in and out, V once
-      yz_fwd : bb * cb * (S + 2 npw)        slab in, psi in (kinetic), H psi out
-      gemm_cn: flops 8 nproj nb npw; bytes cb (nproj + nb) npw
-      gemm_nn: flops 8 nb npw nproj; bytes cb (nproj npw + 2 nb npw)
+    Per step (one H psi over nb bands), with cb = 16 bytes per complex128,
+    S = nslab * N2 * N3 (the slab: grid planes that hold sphere points) and npw
+    sphere points; a step's bytes are divided by the kernel's launches per step.
+      yz_inv : nb cb (npw + S)              read psi, write the slab planes
+      xpass  : nb cb 2 S + launches 8 N     slab in and out, V once per launch
+      yz_fwd : nb cb (S + 2 npw)            slab in, psi in (kinetic), H psi out
+      gemm_cn: flops 8 nproj nb npw         (bytes cb (nproj + nb) npw)
+      gemm_nn: flops 8 nb npw nproj         (bytes cb (nproj npw + 2 nb npw))
     """
     cb = 16
     n1, n2, n3 = prob.fft
@@ -66,17 +68,17 @@ def kernel_model(name, prob, bb, nb):
     m1 = prob.miller[:, 0]
     S = (int(m1.max()) - int(m1.min()) + 1) * n2 * n3
     npj = prob.nproj
-    if name == "yz_inv":
-        return bb * cb * (npw + S), 0
-    if name == "xpass":
-        return bb * cb * 2 * S + 8 * N, 0
-    if name == "yz_fwd":
-        return bb * cb * (S + 2 * npw), 0
-    if name == "gemm_cn":
-        return cb * (npj + nb) * npw, 8 * npj * nb * npw
-    if name == "gemm_nn":
-        return cb * (npj * npw + 2 * nb * npw), 8 * nb * npw * npj
-    return None, None
+    per_step = {
+        "yz_inv": (nb * cb * (npw + S), 0),
+        "xpass": (nb * cb * 2 * S + launches * 8 * N, 0),
+        "yz_fwd": (nb * cb * (S + 2 * npw), 0),
+        "gemm_cn": (cb * (npj + nb) * npw, 8 * npj * nb * npw),
+        "gemm_nn": (cb * (npj * npw + 2 * nb * npw), 8 * nb * npw * npj),
+    }
+    if name not in per_step:
+        return None, None
+    by, fl = per_step[name]
+    return by / launches, fl / launches
 
 
 def source_hash(paths):
@@ -145,10 +147,18 @@ def main():
         for _ in range(steps):
             B.apply_h(dp, x, prec, out=y)
 
-    # warm-up (builds the plan, allocates work space)
+    # warm-up (builds the plan, allocates work space), then the launch-shape autotuner
     run(B.FP64, x64, y64, args.warmup)
     run(B.FP32, x32, y32, args.warmup)
     torch.cuda.synchronize()
+    tuning = None
+    if not args.no_autotune:
+        from paper_2501_08697_amd import autotune
+        cfg32, _ = autotune.tune(dp, x32, precision=B.FP32, use_cache=False)
+        cfg64, ms_tuned = autotune.tune(dp, x64, precision=B.FP64, use_cache=False)
+        tuning = {"fp64": cfg64, "fp32": cfg32}
+        run(B.FP64, x64, y64, args.warmup)
+        torch.cuda.synchronize()
 
     # timed FP64 region, per-kernel HIP events recorded on the library's stream
     B.profile_read()
@@ -174,14 +184,17 @@ def main():
         return a.elapsed_time(b) / args.steps
 
     ms64_clean = timed(B.FP64, x64, y64)
+    if tuning:
+        B.set_tuning(**tuning["fp32"])
     ms32 = timed(B.FP32, x32, y32)
+    if tuning:
+        B.set_tuning(**tuning["fp64"])
 
     # dominant kernel and its roofline
-    bb = min(nb, 32)
     rows = {}
     for name, (n, tot_ms) in kern.items():
         avg = tot_ms / n
-        by, fl = kernel_model(name, prob, bb, nb)
+        by, fl = kernel_model(name, prob, nb, n / args.steps)
         rows[name] = {"launches_per_step": n / args.steps, "avg_ms": avg, "share": tot_ms / (ms64 * args.steps),
                       "alg_bytes": by, "alg_flops": fl}
     dom = max(rows, key=lambda k: rows[k]["avg_ms"] * rows[k]["launches_per_step"])
@@ -221,6 +234,7 @@ def main():
         "fp64_ms_per_step_without_kernel_events": ms64_clean,
         "fp32": {"ms_per_step": ms32, "band_applies_per_s": nb / (ms32 * 1e-3), "speedup_vs_fp64": ms64_clean / ms32},
         "kernels": rows,
+        "tuning": tuning,
     }
 
     if not args.no_davidson:

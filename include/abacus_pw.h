@@ -197,10 +197,15 @@ int abacus_pw_profile_enable(int on);
 int abacus_pw_profile_read(char *buf, int size);
 
 /*
- * Tuning knobs (the autotuner sets these; 0 = library default).
- * band_batch: bands per FFT batch; splitk_chunk: K-chunk of the projection GEMM.
+ * Tuning knobs, process-wide (the autotuner sets these; 0 = library default).
+ * band_batch   bands per local-term batch (slab work space = band_batch planes sets)
+ * splitk_chunk K chunk of the split-K projection GEMM (multiple of 16)
+ * yz_bands     bands handled by one y-z plane work-group
+ * x_bands      bands handled by one x-pass work-group
+ * Results do not depend on the knobs beyond rounding (the split-K chunk changes the
+ * summation grouping of the projections). Returns EBAD_SHAPE for negative values.
  */
-int abacus_pw_set_tuning(int band_batch, int splitk_chunk);
+int abacus_pw_set_tuning(int band_batch, int splitk_chunk, int yz_bands, int x_bands);
 
 #ifdef __cplusplus
 }

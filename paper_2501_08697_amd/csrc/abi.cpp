@@ -114,10 +114,13 @@ int abacus_pw_plan_reset(void) {
     return guarded([&] { return plan_reset_all(); });
 }
 
-int abacus_pw_set_tuning(int band_batch, int splitk_chunk) {
-    if (band_batch < 0 || splitk_chunk < 0) return set_error(ABACUS_PW_EBAD_SHAPE, "negative tuning value");
+int abacus_pw_set_tuning(int band_batch, int splitk_chunk, int yz_bands, int x_bands) {
+    if (band_batch < 0 || splitk_chunk < 0 || yz_bands < 0 || x_bands < 0)
+        return set_error(ABACUS_PW_EBAD_SHAPE, "negative tuning value");
     g_band_batch = band_batch;
     g_splitk_chunk = splitk_chunk;
+    g_yz_bands = yz_bands;
+    g_x_bands = x_bands;
     return ABACUS_PW_OK;
 }
 

@@ -83,6 +83,20 @@ int cholqr_rows(int m, int npw, z64 *T, z64 *Y, Buffers &b, int passes, hipStrea
     return ABACUS_PW_OK;
 }
 
+// Rayleigh-Ritz on the n x n subspace matrix in Hw: lowest nb eigenpairs, then one
+// first-order Lowdin step M = 1.5 I - 0.5 C C^H on the coefficient rows, which
+// turns the inverse-iteration vectors (orthonormal to ~eps ||T|| / gap) into an
+// orthonormal set to O(1e-17). Returns the coefficient rows (ld nmax) in *out.
+int rayleigh_ritz(int n, int nb, int nmax, Buffers &b, z64 **out, hipStream_t st) {
+    z64 *Hw = b.Hw.as<z64>(), *coef = b.coef.as<z64>(), *G = b.G.as<z64>();
+    APW_TRY(heev_lowest(n, Hw, nmax, nb, b.theta.as<double>(), coef, nmax, b.heev.ptr, st));
+    APW_TRY(gemm_cn(0, nb, nb, n, coef, nmax, coef, nmax, G, nb, 1.0, 0.0, b.part.ptr, 0, st));
+    APW_TRY(dav_lowdin(nb, G, st));
+    APW_TRY(gemm_nn(0, nb, n, nb, G, nb, coef, nmax, Hw, nmax, 1.0, 0.0, st));
+    *out = Hw;
+    return ABACUS_PW_OK;
+}
+
 struct Result {
     int iters = 0;
     bool converged = false;
@@ -120,7 +134,7 @@ int davidson_k(const abacus_pw_problem &p, Plan &P, int k, int hprec, int nb, z6
     APW_TRY(b.info.ensure(sizeof(int)));
     APW_TRY(b.heev.ensure(heev_scratch_bytes(nmax)));
     z64 *V = b.V.as<z64>(), *HV = b.HV.as<z64>(), *Xc = b.Xc.as<z64>(), *Wc = b.Wc.as<z64>(), *R = b.R.as<z64>();
-    z64 *Y = b.Y.as<z64>(), *Hs = b.Hs.as<z64>(), *Hw = b.Hw.as<z64>(), *coef = b.coef.as<z64>(), *C = b.C.as<z64>();
+    z64 *Y = b.Y.as<z64>(), *Hs = b.Hs.as<z64>(), *Hw = b.Hw.as<z64>(), *C = b.C.as<z64>();
     double *theta = b.theta.as<double>();
 
     // 1. Cholesky-QR, H X, Rayleigh-Ritz on span(X)
@@ -130,9 +144,10 @@ int davidson_k(const abacus_pw_problem &p, Plan &P, int k, int hprec, int nb, z6
     APW_TRY(gemm_cn(0, nb, nb, npw, Xc, npw, Wc, npw, C, nb, 1.0, 0.0, b.part.ptr, 0, st));
     APW_TRY(dav_hs_append(0, nb, C, nb, Hs, nmax, st));
     APW_TRY(dav_copy_block(nb, Hs, nmax, Hw, nmax, st));
-    APW_TRY(heev_lowest(nb, Hw, nmax, nb, theta, coef, nmax, b.heev.ptr, st));
-    APW_TRY(gemm_nn(0, nb, npw, nb, coef, nmax, Xc, npw, V, npw, 1.0, 0.0, st));
-    APW_TRY(gemm_nn(0, nb, npw, nb, coef, nmax, Wc, npw, HV, npw, 1.0, 0.0, st));
+    z64 *rc = nullptr;
+    APW_TRY(rayleigh_ritz(nb, nb, nmax, b, &rc, st));
+    APW_TRY(gemm_nn(0, nb, npw, nb, rc, nmax, Xc, npw, V, npw, 1.0, 0.0, st));
+    APW_TRY(gemm_nn(0, nb, npw, nb, rc, nmax, Wc, npw, HV, npw, 1.0, 0.0, st));
     APW_TRY(d2d(Xc, V, vb * nb, st));
     APW_TRY(d2d(Wc, HV, vb * nb, st));
     APW_TRY(dav_hs_diag(nb, theta, Hs, nmax, st));
@@ -202,9 +217,9 @@ int davidson_k(const abacus_pw_problem &p, Plan &P, int k, int hprec, int nb, z6
         APW_TRY(gemm_cn(0, n, m, npw, V, npw, HT, npw, C, n, 1.0, 0.0, b.part.ptr, 0, st));
         APW_TRY(dav_hs_append(nbasis, m, C, n, Hs, nmax, st));
         APW_TRY(dav_copy_block(n, Hs, nmax, Hw, nmax, st));
-        APW_TRY(heev_lowest(n, Hw, nmax, nb, theta, coef, nmax, b.heev.ptr, st));
-        APW_TRY(gemm_nn(0, nb, npw, n, coef, nmax, V, npw, Xc, npw, 1.0, 0.0, st));
-        APW_TRY(gemm_nn(0, nb, npw, n, coef, nmax, HV, npw, Wc, npw, 1.0, 0.0, st));
+        APW_TRY(rayleigh_ritz(n, nb, nmax, b, &rc, st));
+        APW_TRY(gemm_nn(0, nb, npw, n, rc, nmax, V, npw, Xc, npw, 1.0, 0.0, st));
+        APW_TRY(gemm_nn(0, nb, npw, n, rc, nmax, HV, npw, Wc, npw, 1.0, 0.0, st));
         nbasis = n;
         ++res.iters;
     }

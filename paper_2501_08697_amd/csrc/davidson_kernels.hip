@@ -116,6 +116,15 @@ __global__ void k_copy_block(int n, const z64 *__restrict__ src, int lds, z64 *_
     }
 }
 
+// M = 1.5 I - 0.5 G (first-order Lowdin factor, in place)
+__global__ void k_lowdin(int n, z64 *G) {
+    const int64_t tot = (int64_t)n * n;
+    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < tot; q += (int64_t)gridDim.x * blockDim.x) {
+        const int i = (int)(q / n), j = (int)(q - (int64_t)i * n);
+        G[q] = z64{(i == j ? 1.5 : 0.0) - 0.5 * G[q].re, -0.5 * G[q].im};
+    }
+}
+
 // G[i][i] += s
 __global__ void k_add_diag(int n, z64 *G, int ld, double s) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -171,6 +180,13 @@ int dav_copy_block(int n, const z64 *src, int lds, z64 *dst, int ldd, hipStream_
     hipLaunchKernelGGL(k_copy_block, dim3((unsigned)std::min<int64_t>(ceil_div64((int64_t)n * n, 256), 4096)),
                        dim3(256), 0, st, n, src, lds, dst, ldd);
     return check_launch("dav_copy_block");
+}
+
+int dav_lowdin(int n, z64 *G, hipStream_t st) {
+    KernelTimer kt("dav_small", st);
+    hipLaunchKernelGGL(k_lowdin, dim3((unsigned)std::min<int64_t>(ceil_div64((int64_t)n * n, 256), 1024)), dim3(256), 0,
+                       st, n, G);
+    return check_launch("dav_lowdin");
 }
 
 int dav_add_diag(int n, z64 *G, int ld, double s, hipStream_t st) {

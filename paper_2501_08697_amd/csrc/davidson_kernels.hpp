@@ -14,6 +14,7 @@ int dav_gather_rows(int m, int npw, const int *idx, const z64 *src, z64 *dst, hi
 int dav_hs_append(int nb0, int m, const z64 *C, int ldc, z64 *Hs, int ld, hipStream_t st);
 int dav_hs_diag(int n, const double *theta, z64 *Hs, int ld, hipStream_t st);
 int dav_copy_block(int n, const z64 *src, int lds, z64 *dst, int ldd, hipStream_t st);
+int dav_lowdin(int n, z64 *G, hipStream_t st);
 int dav_add_diag(int n, z64 *G, int ld, double s, hipStream_t st);
 
 }  // namespace apw

@@ -13,9 +13,12 @@
 //                eigenvalue, each of its 64 lanes evaluating one point of a
 //                65-way multisection of the current bracket.
 //   k_stein      eigenvectors of T by inverse iteration with a pivoted
-//                tridiagonal LU; eigenvalues closer than 1e-3 ||T|| form a
+//                tridiagonal LU; eigenvalues closer than 1e-7 ||T|| form a
 //                cluster handled by one thread, which re-orthogonalises the
 //                cluster's vectors (modified Gram-Schmidt) after every solve.
+//                Between clusters inverse iteration leaves a non-orthogonality
+//                of at most eps ||T|| / gap (2e-9); callers remove it with one
+//                Lowdin step (see the Davidson driver).
 //   k_unmtr      y = Q z for every wanted eigenvector (one work-group each).
 //
 // All matrices are row-major with a leading dimension.
@@ -25,6 +28,7 @@
 namespace apw {
 
 constexpr int kNT = 1024;
+constexpr double kClusterTol = 1e-7;   // relative eigenvalue gap below which vectors are orthogonalised together
 
 __device__ __forceinline__ z64 zconj(z64 a) { return z64{a.re, -a.im}; }
 __device__ __forceinline__ double zabs2(z64 a) { return a.re * a.re + a.im * a.im; }
@@ -246,7 +250,7 @@ __global__ void k_stein(int n, const double *d, const double *e, int nw, const d
     for (int i = 0; i < n; ++i)
         anorm = fmax(anorm, fabs(d[i]) + (i > 0 ? fabs(e[i - 1]) : 0.0) + (i < n - 1 ? fabs(e[i]) : 0.0));
     const double eps = 2.220446049250313e-16;
-    const double ortol = 1e-3 * anorm;
+    const double ortol = kClusterTol * anorm;
     if (j0 > 0 && w[j0] - w[j0 - 1] <= ortol) return;   // not the first of its cluster
     int j1 = j0 + 1;
     while (j1 < nw && w[j1] - w[j1 - 1] <= ortol) ++j1;

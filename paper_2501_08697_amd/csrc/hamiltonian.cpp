@@ -12,7 +12,7 @@
 namespace apw {
 
 int default_band_batch(const Plan &P, int nb) {
-    int bb = g_band_batch > 0 ? g_band_batch : 32;
+    int bb = g_band_batch > 0 ? g_band_batch : 64;
     (void)P;
     return std::max(1, std::min(bb, nb));
 }

@@ -27,34 +27,59 @@ template <typename T> __device__ __forceinline__ cx<T> czero() { return cx<T>{T(
 constexpr int kMaxT3 = 32;     // widest j3 tile of the x pass
 constexpr int kXBands = 4;     // bands per x-pass work-group
 constexpr int kYzThreads = 512; // threads of a y-z plane work-group
+constexpr int kYzBandsDefault = 2; // bands per y-z plane work-group
 
+// One work-group per (plane s, group of bands). The plane's point list is read
+// once into registers; while band b transforms, the sphere values of band b+1
+// are already being fetched.
 template <int N, typename T, typename TIN>
 __global__ __launch_bounds__(kYzThreads) void k_yz_inv(const cx<TIN> *__restrict__ psi, int64_t ldpsi,
-                                                const int *__restrict__ pt_off, const int *__restrict__ pt_g,
-                                                const int *__restrict__ pt_pos, const int *__restrict__ row_off,
-                                                const int *__restrict__ row_list, const cx<T> *__restrict__ tw_g,
-                                                cx<T> *__restrict__ slab, int nslab) {
+                                                       const int *__restrict__ pt_off, const int *__restrict__ pt_g,
+                                                       const int *__restrict__ pt_pos, const int *__restrict__ row_off,
+                                                       const int *__restrict__ row_list, const cx<T> *__restrict__ tw_g,
+                                                       cx<T> *__restrict__ slab, int nslab, int nbands, int bpw) {
+    constexpr int MAXP = 8;   // sphere points per thread held in registers
     extern __shared__ __align__(16) unsigned char smem[];
     cx<T> *plane = reinterpret_cast<cx<T> *>(smem);
     cx<T> *tw = plane + N * N;
-    const int s = blockIdx.x, b = blockIdx.y;
+    const int s = blockIdx.x, b0 = blockIdx.y * bpw, b1 = min(nbands, b0 + bpw);
     const int tid = threadIdx.x, nthr = blockDim.x;
     for (int i = tid; i < N; i += nthr) tw[i] = tw_g[i];
-    for (int i = tid; i < N * N; i += nthr) plane[i] = czero<T>();
-    __syncthreads();
-    const cx<TIN> *x = psi + b * ldpsi;
     const int p0 = pt_off[s], p1 = pt_off[s + 1];
-    for (int p = p0 + tid; p < p1; p += nthr) plane[pt_pos[p]] = cvt<T>(x[pt_g[p]]);
-    __syncthreads();
+    int gi[MAXP], lp[MAXP];
+    cx<TIN> pre[MAXP];
+#pragma unroll
+    for (int q = 0; q < MAXP; ++q) {
+        const int p = p0 + tid + q * nthr;
+        gi[q] = p < p1 ? pt_g[p] : -1;
+        lp[q] = p < p1 ? pt_pos[p] : 0;
+        pre[q] = gi[q] >= 0 ? psi[b0 * ldpsi + gi[q]] : cx<TIN>{TIN(0), TIN(0)};
+    }
     const int r0 = row_off[s], nr = row_off[s + 1] - r0;
-    lds_fft<N, +1, false>(plane, nr, [=](int l) { return row_list[r0 + l] * N; }, 1, tw);
-    lds_fft<N, +1, true>(plane, N, [](int l) { return l; }, N, tw);
-    cx<T> *out = slab + ((int64_t)b * nslab + s) * (int64_t)(N * N);
-    for (int i = tid; i < N * N; i += nthr) out[i] = plane[i];
+    for (int b = b0; b < b1; ++b) {
+        for (int i = tid; i < N * N; i += nthr) plane[i] = czero<T>();
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < MAXP; ++q)
+            if (gi[q] >= 0) plane[lp[q]] = cvt<T>(pre[q]);
+        for (int p = p0 + MAXP * nthr + tid; p < p1; p += nthr) plane[pt_pos[p]] = cvt<T>(psi[b * ldpsi + pt_g[p]]);
+        __syncthreads();
+        if (b + 1 < b1) {
+#pragma unroll
+            for (int q = 0; q < MAXP; ++q)
+                if (gi[q] >= 0) pre[q] = psi[(b + 1) * ldpsi + gi[q]];
+        }
+        lds_fft<N, +1, false>(plane, nr, [=](int l) { return row_list[r0 + l] * N; }, 1, tw);
+        lds_fft<N, +1, true>(plane, N, [](int l) { return l; }, N, tw);
+        cx<T> *out = slab + ((int64_t)b * nslab + s) * (int64_t)(N * N);
+        for (int i = tid; i < N * N; i += nthr) out[i] = plane[i];
+        __syncthreads();
+    }
 }
 
 // One work-group per (j2, a tile of T3 consecutive j3 columns, a group of bands).
-// V of the tile is read once into registers and reused for every band of the group.
+// V of the tile is read once into registers and reused for every band of the
+// group; the next band's slab rows are fetched while the current one transforms.
 template <int N1, typename T, typename TV>
 __global__ __launch_bounds__(256) void k_xpass(cx<T> *__restrict__ slab, int nslab, int N2, int N3, int T3, int nt3,
                                                int nbands, int bpw, const int *__restrict__ row_to_slab,
@@ -68,26 +93,38 @@ __global__ __launch_bounds__(256) void k_xpass(cx<T> *__restrict__ slab, int nsl
     const int b0 = blockIdx.y * bpw, b1 = min(nbands, b0 + bpw);
     const int tid = threadIdx.x, nthr = blockDim.x;
     const int64_t plane = (int64_t)N2 * N3;
+    const int64_t bstride = (int64_t)nslab * plane;
     const int ntile = N1 * w3;
     for (int i = tid; i < N1; i += nthr) tw[i] = tw_g[i];
     T vreg[MAXV];
+    int64_t src[MAXV];      // offset of this thread's element inside a band's slab, or -1
+    cx<T> pre[MAXV];
+    cx<T> *base = slab + (int64_t)j2 * N3 + c0;
 #pragma unroll
     for (int q = 0; q < MAXV; ++q) {
         const int i = tid + q * 256;
         vreg[q] = T(0);
+        src[q] = -1;
         if (i < ntile) {
             const int r = i / w3, c = i - r * w3;
             vreg[q] = static_cast<T>(vloc[(int64_t)r * plane + (int64_t)j2 * N3 + c0 + c]);
+            const int sl = row_to_slab[r];
+            if (sl >= 0) src[q] = sl * plane + c;
         }
+        pre[q] = src[q] >= 0 ? base[b0 * bstride + src[q]] : czero<T>();
     }
     for (int b = b0; b < b1; ++b) {
-        cx<T> *base = slab + (int64_t)b * nslab * plane + (int64_t)j2 * N3 + c0;
-        for (int i = tid; i < ntile; i += nthr) {
-            const int r = i / w3, c = i - r * w3;
-            const int s = row_to_slab[r];
-            tile[i] = s >= 0 ? base[s * plane + c] : czero<T>();
+#pragma unroll
+        for (int q = 0; q < MAXV; ++q) {
+            const int i = tid + q * 256;
+            if (i < ntile) tile[i] = pre[q];
         }
         __syncthreads();
+        if (b + 1 < b1) {
+#pragma unroll
+            for (int q = 0; q < MAXV; ++q)
+                if (src[q] >= 0) pre[q] = base[(b + 1) * bstride + src[q]];
+        }
         lds_fft<N1, +1, true>(tile, w3, [](int l) { return l; }, w3, tw);
 #pragma unroll
         for (int q = 0; q < MAXV; ++q) {
@@ -96,44 +133,71 @@ __global__ __launch_bounds__(256) void k_xpass(cx<T> *__restrict__ slab, int nsl
         }
         __syncthreads();
         lds_fft<N1, -1, true>(tile, w3, [](int l) { return l; }, w3, tw);
-        for (int i = tid; i < ntile; i += nthr) {
-            const int r = i / w3, c = i - r * w3;
-            const int s = row_to_slab[r];
-            if (s >= 0) base[s * plane + c] = tile[i];
+#pragma unroll
+        for (int q = 0; q < MAXV; ++q) {
+            const int i = tid + q * 256;
+            if (src[q] >= 0) base[b * bstride + src[q]] = tile[i];
         }
         __syncthreads();
     }
 }
 
+// One work-group per (plane s, group of bands); the next band's plane is
+// fetched into registers while the current one transforms.
 template <int N, typename T, typename TIO>
 __global__ __launch_bounds__(kYzThreads) void k_yz_fwd(const cx<T> *__restrict__ slab, int nslab,
-                                                const int *__restrict__ pt_off, const int *__restrict__ pt_g,
-                                                const int *__restrict__ pt_pos, const int *__restrict__ row_off,
-                                                const int *__restrict__ row_list, const cx<T> *__restrict__ tw_g,
-                                                const double *__restrict__ kin, const cx<TIO> *__restrict__ psi,
-                                                cx<TIO> *__restrict__ hpsi, int64_t ld, double inv_n) {
+                                                       const int *__restrict__ pt_off, const int *__restrict__ pt_g,
+                                                       const int *__restrict__ pt_pos, const int *__restrict__ row_off,
+                                                       const int *__restrict__ row_list, const cx<T> *__restrict__ tw_g,
+                                                       const double *__restrict__ kin, const cx<TIO> *__restrict__ psi,
+                                                       cx<TIO> *__restrict__ hpsi, int64_t ld, double inv_n,
+                                                       int nbands, int bpw) {
+    constexpr int MAXQ = (N * N + kYzThreads - 1) / kYzThreads;
     extern __shared__ __align__(16) unsigned char smem[];
     cx<T> *plane = reinterpret_cast<cx<T> *>(smem);
     cx<T> *tw = plane + N * N;
-    const int s = blockIdx.x, b = blockIdx.y;
+    const int s = blockIdx.x, b0 = blockIdx.y * bpw, b1 = min(nbands, b0 + bpw);
     const int tid = threadIdx.x, nthr = blockDim.x;
     for (int i = tid; i < N; i += nthr) tw[i] = tw_g[i];
-    const cx<T> *in = slab + ((int64_t)b * nslab + s) * (int64_t)(N * N);
-    for (int i = tid; i < N * N; i += nthr) plane[i] = in[i];
-    __syncthreads();
-    lds_fft<N, -1, true>(plane, N, [](int l) { return l; }, N, tw);
+    cx<T> pre[MAXQ];
+    {
+        const cx<T> *in = slab + ((int64_t)b0 * nslab + s) * (int64_t)(N * N);
+#pragma unroll
+        for (int q = 0; q < MAXQ; ++q) {
+            const int i = tid + q * kYzThreads;
+            pre[q] = i < N * N ? in[i] : czero<T>();
+        }
+    }
     const int r0 = row_off[s], nr = row_off[s + 1] - r0;
-    lds_fft<N, -1, false>(plane, nr, [=](int l) { return row_list[r0 + l] * N; }, 1, tw);
-    const cx<TIO> *x = psi + b * ld;
-    cx<TIO> *y = hpsi + b * ld;
     const int p0 = pt_off[s], p1 = pt_off[s + 1];
     const TIO sc = static_cast<TIO>(inv_n);
-    for (int p = p0 + tid; p < p1; p += nthr) {
-        const int g = pt_g[p];
-        const cx<TIO> v = cvt<TIO>(plane[pt_pos[p]]);
-        const TIO kg = static_cast<TIO>(kin[g]);
-        const cx<TIO> xg = x[g];
-        y[g] = cx<TIO>{kg * xg.re + sc * v.re, kg * xg.im + sc * v.im};
+    for (int b = b0; b < b1; ++b) {
+#pragma unroll
+        for (int q = 0; q < MAXQ; ++q) {
+            const int i = tid + q * kYzThreads;
+            if (i < N * N) plane[i] = pre[q];
+        }
+        __syncthreads();
+        if (b + 1 < b1) {
+            const cx<T> *in = slab + ((int64_t)(b + 1) * nslab + s) * (int64_t)(N * N);
+#pragma unroll
+            for (int q = 0; q < MAXQ; ++q) {
+                const int i = tid + q * kYzThreads;
+                if (i < N * N) pre[q] = in[i];
+            }
+        }
+        lds_fft<N, -1, true>(plane, N, [](int l) { return l; }, N, tw);
+        lds_fft<N, -1, false>(plane, nr, [=](int l) { return row_list[r0 + l] * N; }, 1, tw);
+        const cx<TIO> *x = psi + b * ld;
+        cx<TIO> *y = hpsi + b * ld;
+        for (int p = p0 + tid; p < p1; p += nthr) {
+            const int g = pt_g[p];
+            const cx<TIO> v = cvt<TIO>(plane[pt_pos[p]]);
+            const TIO kg = static_cast<TIO>(kin[g]);
+            const cx<TIO> xg = x[g];
+            y[g] = cx<TIO>{kg * xg.re + sc * v.re, kg * xg.im + sc * v.im};
+        }
+        __syncthreads();
     }
 }
 
@@ -221,7 +285,8 @@ static int launch_yz(bool inverse, const Plan &P, const KTables &K, const void *
     const size_t lds = (size_t)(N * N + N) * sizeof(cx<T>);
     if (lds > kLdsLimit) return set_error(ABACUS_PW_EBAD_FFT_SIZE, "y-z plane does not fit in LDS at this precision");
     const cx<T> *tw = static_cast<const cx<T> *>(sizeof(T) == 8 ? P.tw64[2] : P.tw32[2]);
-    dim3 grid(P.nslab, nbands), block(kYzThreads);
+    const int bpw = g_yz_bands > 0 ? g_yz_bands : kYzBandsDefault;
+    dim3 grid(P.nslab, ceil_div(nbands, bpw)), block(kYzThreads);
     if (inverse) {
         static bool once = false;
         if (!once) {
@@ -231,7 +296,7 @@ static int launch_yz(bool inverse, const Plan &P, const KTables &K, const void *
         KernelTimer kt("yz_inv", st);
         hipLaunchKernelGGL((k_yz_inv<N, T, TIO>), grid, block, lds, st, static_cast<const cx<TIO> *>(psi),
                            (int64_t)K.npw, K.pt_off, K.pt_g, K.pt_pos, K.row_off, K.row_list, tw,
-                           static_cast<cx<T> *>(slab), P.nslab);
+                           static_cast<cx<T> *>(slab), P.nslab, nbands, bpw);
         return check_launch("yz_inv");
     }
     static bool once = false;
@@ -243,7 +308,7 @@ static int launch_yz(bool inverse, const Plan &P, const KTables &K, const void *
     hipLaunchKernelGGL((k_yz_fwd<N, T, TIO>), grid, block, lds, st, static_cast<const cx<T> *>(slab), P.nslab,
                        K.pt_off, K.pt_g, K.pt_pos, K.row_off, K.row_list, tw, K.kin,
                        static_cast<const cx<TIO> *>(psi), static_cast<cx<TIO> *>(hpsi), (int64_t)K.npw,
-                       1.0 / (double)P.N);
+                       1.0 / (double)P.N, nbands, bpw);
     return check_launch("yz_fwd");
 }
 
@@ -264,10 +329,11 @@ static int launch_x(const Plan &P, const void *vloc, void *slab, int nbands, hip
         once = true;
     }
     const cx<T> *tw = static_cast<const cx<T> *>(sizeof(T) == 8 ? P.tw64[0] : P.tw32[0]);
-    dim3 grid(P.N2 * nt3, ceil_div(nbands, kXBands));
+    const int bpw = g_x_bands > 0 ? g_x_bands : kXBands;
+    dim3 grid(P.N2 * nt3, ceil_div(nbands, bpw));
     KernelTimer kt("xpass", st);
     hipLaunchKernelGGL((k_xpass<N1, T, T>), grid, dim3(256), lds, st, static_cast<cx<T> *>(slab), P.nslab, P.N2,
-                       P.N3, T3, nt3, nbands, kXBands, P.row_to_slab, static_cast<const T *>(vloc), tw);
+                       P.N3, T3, nt3, nbands, bpw, P.row_to_slab, static_cast<const T *>(vloc), tw);
     return check_launch("xpass");
 }
 

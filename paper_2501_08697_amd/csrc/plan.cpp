@@ -19,6 +19,8 @@ int lds_split_host(int n, int *a, int *b);   // local_tables.cpp
 
 int g_band_batch = 0;
 int g_splitk_chunk = 0;
+int g_yz_bands = 0;
+int g_x_bands = 0;
 
 DeviceBuffer::~DeviceBuffer() {
     if (ptr) (void)hipFree(ptr);

@@ -84,9 +84,11 @@ struct Plan {
     DeviceBuffer tmp_io;      // precision staging
 };
 
-// Global tuning knobs (abacus_pw_set_tuning).
-extern int g_band_batch;
-extern int g_splitk_chunk;
+// Global tuning knobs (abacus_pw_set_tuning); 0 selects the library default.
+extern int g_band_batch;    // bands per local-term batch
+extern int g_splitk_chunk;  // K chunk of the split-K projection GEMM
+extern int g_yz_bands;      // bands per y-z plane work-group
+extern int g_x_bands;       // bands per x-pass work-group
 
 // Looks up or builds the plan for a problem (validates it on build).
 int get_plan(const abacus_pw_problem *p, Plan **out);
