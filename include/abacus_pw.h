@@ -72,7 +72,7 @@ extern "C" {
 /* Arithmetic modes (the `precision` argument). */
 #define ABACUS_PW_FP64        0  /* complex128 psi; FP64 FFTs and GEMMs */
 #define ABACUS_PW_FP32        1  /* complex64 psi; FP32 FFTs and FP32-MFMA GEMMs with FP32 accumulation */
-#define ABACUS_PW_MIXED_BF16  2  /* complex128 psi in and out; FP32 FFTs; BF16 GEMM operands, FP32 accumulation */
+#define ABACUS_PW_MIXED_BF16  2  /* complex128 psi in and out; FP32 FFTs; BF16 projector GEMM operands, FP32 accumulation */
 #define ABACUS_PW_MIXED_FP32  3  /* complex128 psi in and out; FP32 FFTs; FP32 GEMM operands, FP32 accumulation */
 
 /* problem.flags */
@@ -135,8 +135,8 @@ int abacus_pw_apply_h(const abacus_pw_problem *p, int precision, int nb, const v
 
 /*
  * Lowest nb eigenpairs of H at every k-point by block Davidson (Sec. III.B
- * names Davidson as the eigensolver of the plane-wave code; the steps are the
- * library's, listed in the design notes): residuals R = H Psi - Psi Lambda,
+ * names Davidson as the eigensolver of the plane-wave code without its steps;
+ * the steps below are the library's): residuals R = H Psi - Psi Lambda,
  * Teter-Payne-Allan preconditioned corrections for unconverged bands, two
  * classical Gram-Schmidt passes against the basis, Cholesky-QR, Rayleigh-Ritz
  * on the basis [Psi, T] (restarted to the Ritz vectors when it would exceed
@@ -202,10 +202,13 @@ int abacus_pw_profile_read(char *buf, int size);
  * splitk_chunk K chunk of the split-K projection GEMM (multiple of 16)
  * yz_bands     bands handled by one y-z plane work-group
  * x_bands      bands handled by one x-pass work-group
+ * yz_mode      y-z plane kernels: 0 automatic (whole plane in LDS when it fits), 1 whole
+ *              plane, 2 compact (only the plane's z-column rows in LDS, y transforms in
+ *              j3 chunks); planes that do not fit whole always use the compact form
  * Results do not depend on the knobs beyond rounding (the split-K chunk changes the
- * summation grouping of the projections). Returns EBAD_SHAPE for negative values.
+ * summation grouping of the projections). Returns EBAD_SHAPE for invalid values.
  */
-int abacus_pw_set_tuning(int band_batch, int splitk_chunk, int yz_bands, int x_bands);
+int abacus_pw_set_tuning(int band_batch, int splitk_chunk, int yz_bands, int x_bands, int yz_mode);
 
 #ifdef __cplusplus
 }

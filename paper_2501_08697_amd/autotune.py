@@ -20,12 +20,13 @@ import os
 from . import binding as B
 
 CANDIDATES = {
+    "yz_mode": [1, 2],
     "band_batch": [32, 64, 128],
     "yz_bands": [1, 2, 4],
     "x_bands": [2, 4, 8],
     "splitk_chunk": [256, 512, 1024],
 }
-DEFAULT = {"band_batch": 0, "splitk_chunk": 0, "yz_bands": 0, "x_bands": 0}
+DEFAULT = {"band_batch": 0, "splitk_chunk": 0, "yz_bands": 0, "x_bands": 0, "yz_mode": 0}
 
 
 def cache_path() -> str:
@@ -38,7 +39,7 @@ def key(dp: B.DeviceProblem, nb: int, precision: int) -> str:
 
 
 def _apply(cfg):
-    B.set_tuning(cfg["band_batch"], cfg["splitk_chunk"], cfg["yz_bands"], cfg["x_bands"])
+    B.set_tuning(cfg["band_batch"], cfg["splitk_chunk"], cfg["yz_bands"], cfg["x_bands"], cfg.get("yz_mode", 0))
 
 
 def _time(dp, x, y, nb, precision, reps):

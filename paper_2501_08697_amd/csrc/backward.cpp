@@ -44,23 +44,18 @@ int apply_h_backward_all(const abacus_pw_problem &p, Plan &P, int prec, int nb, 
     }
     if (grad_v) {
         const int bb = default_band_batch(P, nb);
-        const size_t sb = local_slab_bytes(P, fp, bb);
+        const size_t sb = local_slab_bytes(P, fp, P.nk * bb);
         APW_TRY(P.slab.ensure(sb));
         APW_TRY(P.slab2.ensure(sb));
         APW_TRY(P.gradv_part.ensure(sizeof(double) * (size_t)kGradVGroups * P.N));
         int first = 1;
-        for (int k = 0; k < P.nk; ++k) {
-            const KTables &K = P.k[k];
-            for (int b0 = 0; b0 < nb; b0 += bb) {
-                const int n = std::min(bb, nb - b0);
-                const char *xk = static_cast<const char *>(psi) + ((size_t)nb * K.pw_off + (size_t)b0 * K.npw) * ib;
-                const char *yk = static_cast<const char *>(dy) + ((size_t)nb * K.pw_off + (size_t)b0 * K.npw) * ib;
-                APW_TRY(local_inverse_planes(P, k, fp, io, xk, P.slab.ptr, n, st));
-                APW_TRY(local_inverse_planes(P, k, fp, io, yk, P.slab2.ptr, n, st));
-                APW_TRY(local_gradv_accumulate(P, fp, P.slab.ptr, P.slab2.ptr, n, P.gradv_part.as<double>(),
-                                               kGradVGroups, first, st));
-                first = 0;
-            }
+        for (int b0 = 0; b0 < nb; b0 += bb) {
+            const int n = std::min(bb, nb - b0);
+            APW_TRY(local_inverse_planes(P, 0, P.nk, nb, b0, n, fp, io, psi, P.slab.ptr, st));
+            APW_TRY(local_inverse_planes(P, 0, P.nk, nb, b0, n, fp, io, dy, P.slab2.ptr, st));
+            APW_TRY(local_gradv_accumulate(P, fp, P.slab.ptr, P.slab2.ptr, P.nk * n, P.gradv_part.as<double>(),
+                                           kGradVGroups, first, st));
+            first = 0;
         }
         APW_TRY(local_gradv_finish(P, P.gradv_part.as<double>(), kGradVGroups, grad_v, st));
     }

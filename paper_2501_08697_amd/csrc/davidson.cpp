@@ -235,21 +235,21 @@ int davidson_k(const abacus_pw_problem &p, Plan &P, int k, int hprec, int nb, z6
 
 int davidson_all(const abacus_pw_problem &p, Plan &P, int prec, int nb, void *psi, double *eig, double tol,
                  int max_iter, int ndim, int *iters, double *resid, hipStream_t st) {
-    if (prec == ABACUS_PW_MIXED_BF16)
-        return set_error(ABACUS_PW_EBAD_PRECISION, "MIXED_BF16 Davidson is not offered by this build");
     APW_TRY(local_supported(P, 0));   // the refinement phase always runs FP64 transforms
     Buffers b;
     bool all = true;
     std::vector<double> th, rn;
     // operator copies once per solve (the reduced-precision phase reads them)
-    APW_TRY(operator_copies(p, P, prec != ABACUS_PW_FP64, prec != ABACUS_PW_FP64, st));
+    APW_TRY(operator_copies(p, P, prec != ABACUS_PW_FP64, prec == ABACUS_PW_MIXED_FP32, st,
+                            prec == ABACUS_PW_MIXED_BF16));
     for (int k = 0; k < P.nk; ++k) {
         z64 *X = static_cast<z64 *>(psi) + (size_t)nb * P.k[k].pw_off;
         int total = 0;
         Result r;
-        if (prec == ABACUS_PW_MIXED_FP32) {
-            APW_TRY(davidson_k(p, P, k, ABACUS_PW_MIXED_FP32, nb, X, b, std::max(tol, 1e-5), max_iter, ndim, 3, th, rn,
-                               r, st));
+        if (prec != ABACUS_PW_FP64) {
+            // reduced-precision phase: stop at its noise floor (FP32 ~1e-5, BF16 projectors ~1e-3) or on stagnation
+            const double tol_a = std::max(tol, prec == ABACUS_PW_MIXED_BF16 ? 1e-3 : 1e-5);
+            APW_TRY(davidson_k(p, P, k, prec, nb, X, b, tol_a, max_iter, ndim, 3, th, rn, r, st));
             total += r.iters;
         }
         APW_TRY(davidson_k(p, P, k, ABACUS_PW_FP64, nb, X, b, tol, std::max(0, max_iter - total), ndim, 0, th, rn, r,

@@ -60,17 +60,25 @@ __global__ __launch_bounds__(256) void k_gemm_cn_part(int M, int N, int K, int k
         for (int b = 0; b < 2; ++b) cre[a][b] = cim[a][b] = Acc<T>::zero();
     const int lr = tid >> 2, lk = (tid & 3) * 4;   // loader: row, first k of 4
     const int wi = (w & 1) * 32, wj = (w >> 1) * 32;
-    for (int k0 = kb; k0 < ke; k0 += KT) {
-        {
-            const int gi = i0 + lr, gj = j0 + lr;
+    const int gi = i0 + lr, gj = j0 + lr;
+    cx<T> ra[4], rb[4];
+    auto load = [&](int k0) {
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const int gk = k0 + lk + q;
-                As[lr][lk + q] = (gi < M && gk < ke) ? A[gi * lda + gk] : cx<T>{T(0), T(0)};
-                Bs[lr][lk + q] = (gj < N && gk < ke) ? B[gj * ldb + gk] : cx<T>{T(0), T(0)};
-            }
+        for (int q = 0; q < 4; ++q) {
+            const int gk = k0 + lk + q;
+            ra[q] = (gi < M && gk < ke) ? A[gi * lda + gk] : cx<T>{T(0), T(0)};
+            rb[q] = (gj < N && gk < ke) ? B[gj * ldb + gk] : cx<T>{T(0), T(0)};
+        }
+    };
+    load(kb);
+    for (int k0 = kb; k0 < ke; k0 += KT) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            As[lr][lk + q] = ra[q];
+            Bs[lr][lk + q] = rb[q];
         }
         __syncthreads();
+        if (k0 + KT < ke) load(k0 + KT);   // next stage in flight while this one multiplies
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
             const int kk = 4 * q + (lane >> 4);
@@ -182,22 +190,30 @@ __global__ __launch_bounds__(256) void k_gemm_nn(int M, int G, int K, const cx<T
     const int wj = (w & 1) * 32, wg = (w >> 1) * 32;
     const int ar = tid >> 2, ak = (tid & 3) * 4;       // A loader: row j, 4 consecutive i
     const int bk = tid >> 4, bg = (tid & 15) * 4;      // B loader: row i, 4 consecutive g
+    cx<T> ra[4], rb[4];
+    auto load = [&](int k0) {
+        const int gj = j0 + ar;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int gk = k0 + ak + q;
+            ra[q] = (gj < M && gk < K) ? A[gj * lda + gk] : cx<T>{T(0), T(0)};
+        }
+        const int gk = k0 + bk;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int gg = g0 + bg + q;
+            rb[q] = (gk < K && gg < G) ? B[gk * ldb + gg] : cx<T>{T(0), T(0)};
+        }
+    };
+    load(0);
     for (int k0 = 0; k0 < K; k0 += KT) {
-        {
-            const int gj = j0 + ar;
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const int gk = k0 + ak + q;
-                As[ar][ak + q] = (gj < M && gk < K) ? A[gj * lda + gk] : cx<T>{T(0), T(0)};
-            }
-            const int gk = k0 + bk;
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const int gg = g0 + bg + q;
-                Bs[bk][bg + q] = (gk < K && gg < G) ? B[gk * ldb + gg] : cx<T>{T(0), T(0)};
-            }
+        for (int q = 0; q < 4; ++q) {
+            As[ar][ak + q] = ra[q];
+            Bs[bk][bg + q] = rb[q];
         }
         __syncthreads();
+        if (k0 + KT < K) load(k0 + KT);   // next stage in flight while this one multiplies
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
             const int kk = 4 * q + (lane >> 4);
@@ -358,6 +374,16 @@ int gemm_nn(int prec, int M, int G, int K, const void *A, int64_t lda, const voi
 int gemm_nn_f32_into_f64(int M, int G, int K, const void *A, int64_t lda, const void *B, int64_t ldb, void *C,
                          int64_t ldc, double alpha, double beta, hipStream_t st) {
     return gemm_nn_t<float, double>(M, G, K, A, lda, B, ldb, C, ldc, alpha, beta, st);
+}
+
+int reduce_dapply_f32(int M, int N, int nsplit, const void *part, const double *dmat, const int *blo, const int *bn,
+                      const int *bdoff, void *Q, hipStream_t st) {
+    const size_t lds = (size_t)M * sizeof(cx<double>);
+    if (lds > 64 * 1024) return set_error(ABACUS_PW_EBAD_SHAPE, "too many projectors for the D-apply stage");
+    KernelTimer kt("reduce_dapply", st);
+    hipLaunchKernelGGL(k_reduce_dapply<float>, dim3(N), dim3(256), lds, st, M, nsplit, static_cast<const c32 *>(part),
+                       N, dmat, blo, bn, bdoff, static_cast<c32 *>(nullptr), static_cast<c32 *>(Q));
+    return check_launch("reduce_dapply");
 }
 
 int grad_d_accumulate(int prec, int nb, int M, const void *P, const void *Q, const int *blo, const int *bn,

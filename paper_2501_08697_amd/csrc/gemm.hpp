@@ -30,4 +30,21 @@ int gemm_nn_f32_into_f64(int M, int G, int K, const void *A, int64_t lda, const 
 int grad_d_accumulate(int prec, int nb, int M, const void *P, const void *Q, const int *blo, const int *bn,
                       const int *bdoff, double *gd, int first, hipStream_t st);
 
+// Split-K sum of complex64 partials [nsplit][N][M] followed by the D blocks: Q[j][i] (complex64).
+int reduce_dapply_f32(int M, int N, int nsplit, const void *part, const double *dmat, const int *blo, const int *bn,
+                      const int *bdoff, void *Q, hipStream_t st);
+
+// ---- BF16 operands, FP32 accumulation (gemm_bf16.hip) ----
+// out[i] = complex128 in[i] rounded to a packed bf16 pair (re low, im high).
+int pack_bf16(int64_t n, const void *in, void *out, hipStream_t st);
+size_t gemm_cn_bf16_part_bytes(int M, int N, int K, int chunk_hint);
+// Q[j][i] = sum_t D_blk(i) P[j][.], P[j][i] = <beta_i|psi_j> with bf16 operands (Bpk packed bf16 beta,
+// psi complex128 when psi_is_f64 else complex64); Q complex64 [N][M].
+int proj_dapply_bf16(int M, int N, int K, const void *Bpk, int64_t ldb, const void *psi, int psi_is_f64, int64_t ldp,
+                     const double *dmat, const int *blo, const int *bn, const int *bdoff, void *Q, void *part,
+                     int chunk_hint, hipStream_t st);
+// C[j][g] += sum_i A[j][i] B[i][g], A complex64, B packed bf16, C complex128.
+int gemm_nn_bf16_into_f64(int M, int G, int K, const void *A, int64_t lda, const void *Bpk, int64_t ldb, void *C,
+                          int64_t ldc, hipStream_t st);
+
 }  // namespace apw

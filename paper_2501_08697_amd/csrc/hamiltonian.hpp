@@ -6,12 +6,17 @@
 namespace apw {
 
 int default_band_batch(const Plan &P, int nb);
-int operator_copies(const abacus_pw_problem &p, Plan &P, bool need_v32, bool need_b32, hipStream_t st);
+int operator_copies(const abacus_pw_problem &p, Plan &P, bool need_v32, bool need_b32, hipStream_t st,
+                    bool need_bf = false);
 
 // hpsi = H psi for nb bands of k-point k ([nb][npw_k] blocks). refresh_copies re-derives the
 // reduced-precision copies of V and beta (unless the problem is flagged static).
 int apply_h_k(const abacus_pw_problem &p, Plan &P, int k, int prec, int nb, const void *psi, void *hpsi,
               hipStream_t st, bool refresh_copies = true);
+
+// hpsi = H psi for nb bands at the k-points [k0, k1) (psi starts at k0's block).
+int apply_h_range(const abacus_pw_problem &p, Plan &P, int k0, int k1, int prec, int nb, const void *psi, void *hpsi,
+                  hipStream_t st, bool refresh_copies);
 
 // hpsi = H psi for nb bands at every k-point (packed [k][nb][npw_k]).
 int apply_h_all(const abacus_pw_problem &p, Plan &P, int prec, int nb, const void *psi, void *hpsi, hipStream_t st);

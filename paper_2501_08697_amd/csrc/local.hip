@@ -24,6 +24,26 @@ namespace apw {
 
 template <typename T> __device__ __forceinline__ cx<T> czero() { return cx<T>{T(0), T(0)}; }
 
+// A band batch spread over the k-points [k0, k0 + nk) of a call: at every k the
+// bands [b0, b0 + bbt) of that k's [nb_total][npw_k] block; off0 = pw_off[k0].
+struct BatchArgs {
+    int64_t nb_total;
+    int64_t off0;
+    int b0;
+    int bbt;
+};
+
+// Block y index -> (k-point, band range inside the batch) for work-groups of bpw bands.
+__device__ __forceinline__ void batch_block(const KDesc *kd, const BatchArgs &ba, int bpw, KDesc &D, int &k, int &lb0,
+                                            int &lb1) {
+    const int gpk = (ba.bbt + bpw - 1) / bpw;
+    k = blockIdx.y / gpk;
+    const int g = blockIdx.y - k * gpk;
+    D = kd[k];
+    lb0 = g * bpw;
+    lb1 = min(ba.bbt, lb0 + bpw);
+}
+
 constexpr int kMaxT3 = 32;     // widest j3 tile of the x pass
 constexpr int kXBands = 4;     // bands per x-pass work-group
 constexpr int kYzThreads = 512; // threads of a y-z plane work-group
@@ -33,16 +53,22 @@ constexpr int kYzBandsDefault = 2; // bands per y-z plane work-group
 // once into registers; while band b transforms, the sphere values of band b+1
 // are already being fetched.
 template <int N, typename T, typename TIN>
-__global__ __launch_bounds__(kYzThreads) void k_yz_inv(const cx<TIN> *__restrict__ psi, int64_t ldpsi,
-                                                       const int *__restrict__ pt_off, const int *__restrict__ pt_g,
-                                                       const int *__restrict__ pt_pos, const int *__restrict__ row_off,
-                                                       const int *__restrict__ row_list, const cx<T> *__restrict__ tw_g,
-                                                       cx<T> *__restrict__ slab, int nslab, int nbands, int bpw) {
+__global__ __launch_bounds__(kYzThreads) void k_yz_inv(const cx<TIN> *__restrict__ psi_all, const KDesc *__restrict__ kd,
+                                                       BatchArgs ba, const cx<T> *__restrict__ tw_g,
+                                                       cx<T> *__restrict__ slab, int nslab, int bpw) {
+    KDesc D;
+    int kk, b0, b1;
+    batch_block(kd, ba, bpw, D, kk, b0, b1);
+    const int *__restrict__ pt_off = D.pt_off, *__restrict__ pt_g = D.pt_g, *__restrict__ pt_pos = D.pt_pos;
+    const int *__restrict__ row_off = D.row_off, *__restrict__ row_list = D.row_list;
+    const cx<TIN> *psi = psi_all + ba.nb_total * (D.pw_off - ba.off0) + (int64_t)ba.b0 * D.npw;
+    const int64_t ldpsi = D.npw;
+    slab += (int64_t)kk * ba.bbt * nslab * (int64_t)(N * N);
     constexpr int MAXP = 8;   // sphere points per thread held in registers
     extern __shared__ __align__(16) unsigned char smem[];
     cx<T> *plane = reinterpret_cast<cx<T> *>(smem);
     cx<T> *tw = plane + N * N;
-    const int s = blockIdx.x, b0 = blockIdx.y * bpw, b1 = min(nbands, b0 + bpw);
+    const int s = blockIdx.x;
     const int tid = threadIdx.x, nthr = blockDim.x;
     for (int i = tid; i < N; i += nthr) tw[i] = tw_g[i];
     const int p0 = pt_off[s], p1 = pt_off[s + 1];
@@ -146,17 +172,25 @@ __global__ __launch_bounds__(256) void k_xpass(cx<T> *__restrict__ slab, int nsl
 // fetched into registers while the current one transforms.
 template <int N, typename T, typename TIO>
 __global__ __launch_bounds__(kYzThreads) void k_yz_fwd(const cx<T> *__restrict__ slab, int nslab,
-                                                       const int *__restrict__ pt_off, const int *__restrict__ pt_g,
-                                                       const int *__restrict__ pt_pos, const int *__restrict__ row_off,
-                                                       const int *__restrict__ row_list, const cx<T> *__restrict__ tw_g,
-                                                       const double *__restrict__ kin, const cx<TIO> *__restrict__ psi,
-                                                       cx<TIO> *__restrict__ hpsi, int64_t ld, double inv_n,
-                                                       int nbands, int bpw) {
+                                                       const KDesc *__restrict__ kd, BatchArgs ba,
+                                                       const cx<T> *__restrict__ tw_g, const cx<TIO> *__restrict__ psi_all,
+                                                       cx<TIO> *__restrict__ hpsi_all, double inv_n, int bpw) {
+    KDesc D;
+    int kk, b0, b1;
+    batch_block(kd, ba, bpw, D, kk, b0, b1);
+    const int *__restrict__ pt_off = D.pt_off, *__restrict__ pt_g = D.pt_g, *__restrict__ pt_pos = D.pt_pos;
+    const int *__restrict__ row_off = D.row_off, *__restrict__ row_list = D.row_list;
+    const double *__restrict__ kin = D.kin;
+    const int64_t koff = ba.nb_total * (D.pw_off - ba.off0) + (int64_t)ba.b0 * D.npw;
+    const cx<TIO> *psi = psi_all + koff;
+    cx<TIO> *hpsi = hpsi_all + koff;
+    const int64_t ld = D.npw;
+    slab += (int64_t)kk * ba.bbt * nslab * (int64_t)(N * N);
     constexpr int MAXQ = (N * N + kYzThreads - 1) / kYzThreads;
     extern __shared__ __align__(16) unsigned char smem[];
     cx<T> *plane = reinterpret_cast<cx<T> *>(smem);
     cx<T> *tw = plane + N * N;
-    const int s = blockIdx.x, b0 = blockIdx.y * bpw, b1 = min(nbands, b0 + bpw);
+    const int s = blockIdx.x;
     const int tid = threadIdx.x, nthr = blockDim.x;
     for (int i = tid; i < N; i += nthr) tw[i] = tw_g[i];
     cx<T> pre[MAXQ];
@@ -193,6 +227,123 @@ __global__ __launch_bounds__(kYzThreads) void k_yz_fwd(const cx<T> *__restrict__
         for (int p = p0 + tid; p < p1; p += nthr) {
             const int g = pt_g[p];
             const cx<TIO> v = cvt<TIO>(plane[pt_pos[p]]);
+            const TIO kg = static_cast<TIO>(kin[g]);
+            const cx<TIO> xg = x[g];
+            y[g] = cx<TIO>{kg * xg.re + sc * v.re, kg * xg.im + sc * v.im};
+        }
+        __syncthreads();
+    }
+}
+
+// Compact-row variants of the plane passes for planes too large for LDS (and
+// for higher occupancy): only the nr rows of the plane that hold sphere columns
+// are kept in LDS (rows[r][j3], r = position in the plane's row list); the y
+// transforms run through an N2 x C chunk buffer, C consecutive j3 at a time.
+template <int N, typename T, typename TIN>
+__global__ __launch_bounds__(256) void k_yz_inv_c(const cx<TIN> *__restrict__ psi_all, const KDesc *__restrict__ kd,
+                                                  BatchArgs ba, const cx<T> *__restrict__ tw_g,
+                                                  cx<T> *__restrict__ slab, int nslab, int bpw, int rows_max, int C) {
+    KDesc D;
+    int kk, b0, b1;
+    batch_block(kd, ba, bpw, D, kk, b0, b1);
+    const int *__restrict__ pt_off = D.pt_off, *__restrict__ pt_g = D.pt_g, *__restrict__ pt_pos = D.pt_pos;
+    const int *__restrict__ row_off = D.row_off, *__restrict__ row_list = D.row_list;
+    const cx<TIN> *psi = psi_all + ba.nb_total * (D.pw_off - ba.off0) + (int64_t)ba.b0 * D.npw;
+    const int64_t ldpsi = D.npw;
+    slab += (int64_t)kk * ba.bbt * nslab * (int64_t)(N * N);
+    extern __shared__ __align__(16) unsigned char smem[];
+    cx<T> *rows = reinterpret_cast<cx<T> *>(smem);
+    cx<T> *ybuf = rows + rows_max * N;
+    cx<T> *tw = ybuf + N * C;
+    int *map = reinterpret_cast<int *>(tw + N);
+    const int s = blockIdx.x;
+    const int tid = threadIdx.x, nthr = blockDim.x;
+    const int r0 = row_off[s], nr = row_off[s + 1] - r0;
+    const int p0 = pt_off[s], p1 = pt_off[s + 1];
+    for (int i = tid; i < N; i += nthr) tw[i] = tw_g[i];
+    for (int r = tid; r < nr; r += nthr) map[row_list[r0 + r]] = r;
+    __syncthreads();
+    for (int b = b0; b < b1; ++b) {
+        for (int i = tid; i < nr * N; i += nthr) rows[i] = czero<T>();
+        __syncthreads();
+        for (int p = p0 + tid; p < p1; p += nthr) {
+            const int pos = pt_pos[p], slot = pos / N;
+            rows[map[slot] * N + (pos - slot * N)] = cvt<T>(psi[b * ldpsi + pt_g[p]]);
+        }
+        __syncthreads();
+        lds_fft<N, +1, false>(rows, nr, [](int l) { return l * N; }, 1, tw);
+        cx<T> *out = slab + ((int64_t)b * nslab + s) * (int64_t)(N * N);
+        for (int c0 = 0; c0 < N; c0 += C) {
+            const int w = min(C, N - c0);
+            for (int i = tid; i < N * w; i += nthr) ybuf[(i / w) * C + (i % w)] = czero<T>();
+            __syncthreads();
+            for (int i = tid; i < nr * w; i += nthr) {
+                const int r = i / w, c = i - r * w;
+                ybuf[row_list[r0 + r] * C + c] = rows[r * N + c0 + c];
+            }
+            __syncthreads();
+            lds_fft<N, +1, true>(ybuf, w, [](int l) { return l; }, C, tw);
+            for (int i = tid; i < N * w; i += nthr) {
+                const int j2 = i / w, c = i - j2 * w;
+                out[j2 * N + c0 + c] = ybuf[j2 * C + c];
+            }
+            __syncthreads();
+        }
+    }
+}
+
+template <int N, typename T, typename TIO>
+__global__ __launch_bounds__(256) void k_yz_fwd_c(const cx<T> *__restrict__ slab, int nslab,
+                                                  const KDesc *__restrict__ kd, BatchArgs ba,
+                                                  const cx<T> *__restrict__ tw_g, const cx<TIO> *__restrict__ psi_all,
+                                                  cx<TIO> *__restrict__ hpsi_all, double inv_n, int bpw, int rows_max,
+                                                  int C) {
+    KDesc D;
+    int kk, b0, b1;
+    batch_block(kd, ba, bpw, D, kk, b0, b1);
+    const int *__restrict__ pt_off = D.pt_off, *__restrict__ pt_g = D.pt_g, *__restrict__ pt_pos = D.pt_pos;
+    const int *__restrict__ row_off = D.row_off, *__restrict__ row_list = D.row_list;
+    const double *__restrict__ kin = D.kin;
+    const int64_t koff = ba.nb_total * (D.pw_off - ba.off0) + (int64_t)ba.b0 * D.npw;
+    const cx<TIO> *psi = psi_all + koff;
+    cx<TIO> *hpsi = hpsi_all + koff;
+    const int64_t ld = D.npw;
+    slab += (int64_t)kk * ba.bbt * nslab * (int64_t)(N * N);
+    extern __shared__ __align__(16) unsigned char smem[];
+    cx<T> *rows = reinterpret_cast<cx<T> *>(smem);
+    cx<T> *ybuf = rows + rows_max * N;
+    cx<T> *tw = ybuf + N * C;
+    int *map = reinterpret_cast<int *>(tw + N);
+    const int s = blockIdx.x;
+    const int tid = threadIdx.x, nthr = blockDim.x;
+    const int r0 = row_off[s], nr = row_off[s + 1] - r0;
+    const int p0 = pt_off[s], p1 = pt_off[s + 1];
+    const TIO sc = static_cast<TIO>(inv_n);
+    for (int i = tid; i < N; i += nthr) tw[i] = tw_g[i];
+    for (int r = tid; r < nr; r += nthr) map[row_list[r0 + r]] = r;
+    __syncthreads();
+    for (int b = b0; b < b1; ++b) {
+        const cx<T> *in = slab + ((int64_t)b * nslab + s) * (int64_t)(N * N);
+        for (int c0 = 0; c0 < N; c0 += C) {
+            const int w = min(C, N - c0);
+            for (int i = tid; i < N * w; i += nthr) {
+                const int j2 = i / w, c = i - j2 * w;
+                ybuf[j2 * C + c] = in[j2 * N + c0 + c];
+            }
+            __syncthreads();
+            lds_fft<N, -1, true>(ybuf, w, [](int l) { return l; }, C, tw);
+            for (int i = tid; i < nr * w; i += nthr) {
+                const int r = i / w, c = i - r * w;
+                rows[r * N + c0 + c] = ybuf[row_list[r0 + r] * C + c];
+            }
+            __syncthreads();
+        }
+        lds_fft<N, -1, false>(rows, nr, [](int l) { return l * N; }, 1, tw);
+        const cx<TIO> *x = psi + b * ld;
+        cx<TIO> *y = hpsi + b * ld;
+        for (int p = p0 + tid; p < p1; p += nthr) {
+            const int g = pt_g[p], pos = pt_pos[p], slot = pos / N;
+            const cx<TIO> v = cvt<TIO>(rows[map[slot] * N + (pos - slot * N)]);
             const TIO kg = static_cast<TIO>(kin[g]);
             const cx<TIO> xg = x[g];
             y[g] = cx<TIO>{kg * xg.re + sc * v.re, kg * xg.im + sc * v.im};
@@ -279,36 +430,78 @@ template <typename K> static int allow_lds(K kernel, size_t bytes) {
 
 constexpr size_t kLdsLimit = 160 * 1024;
 
+// LDS bytes of the compact-row plane kernels with chunk width C.
+template <int N, typename T> static size_t compact_lds(int rows_max, int C) {
+    return (size_t)(rows_max * N + N * C + N) * sizeof(cx<T>) + (size_t)N * sizeof(int);
+}
+
+// Chunk width for the compact kernels: the widest C <= 32 that fits (prefers two
+// work-groups per CU when that still allows C >= 8). 0 when nothing fits.
+template <int N, typename T> static int compact_chunk(int rows_max) {
+    for (int C = std::min(32, N); C >= 8; C -= 8)
+        if (compact_lds<N, T>(rows_max, C) <= kLdsLimit / 2) return C;
+    for (int C = std::min(32, N); C >= 4; C -= 4)
+        if (compact_lds<N, T>(rows_max, C) <= kLdsLimit) return C;
+    return 0;
+}
+
+// One launch of a plane pass over the k-points [k0, k0 + nkb) of the batch ba.
 template <int N, typename T, typename TIO>
-static int launch_yz(bool inverse, const Plan &P, const KTables &K, const void *psi, void *hpsi, void *slab,
-                     int nbands, hipStream_t st) {
-    const size_t lds = (size_t)(N * N + N) * sizeof(cx<T>);
-    if (lds > kLdsLimit) return set_error(ABACUS_PW_EBAD_FFT_SIZE, "y-z plane does not fit in LDS at this precision");
+static int launch_yz(bool inverse, const Plan &P, int k0, int nkb, const BatchArgs &ba, const void *psi,
+                     void *hpsi, void *slab, hipStream_t st) {
+    const size_t lds_full = (size_t)(N * N + N) * sizeof(cx<T>);
+    const int Cc = compact_chunk<N, T>(P.max_rows);
+    const bool full_fits = lds_full <= kLdsLimit;
+    const bool compact = g_yz_mode == 2 || !full_fits;
+    if (compact && Cc == 0) return set_error(ABACUS_PW_EBAD_FFT_SIZE, "y-z plane rows do not fit in LDS at this precision");
     const cx<T> *tw = static_cast<const cx<T> *>(sizeof(T) == 8 ? P.tw64[2] : P.tw32[2]);
-    const int bpw = g_yz_bands > 0 ? g_yz_bands : kYzBandsDefault;
-    dim3 grid(P.nslab, ceil_div(nbands, bpw)), block(kYzThreads);
+    const KDesc *kd = P.kdesc + k0;
+    const int bpw = std::min(ba.bbt, g_yz_bands > 0 ? g_yz_bands : kYzBandsDefault);
+    const dim3 grid(P.nslab, nkb * ceil_div(ba.bbt, bpw));
+    if (compact) {
+        const size_t lds = compact_lds<N, T>(P.max_rows, Cc);
+        if (inverse) {
+            static bool once = false;
+            if (!once) {
+                APW_TRY(allow_lds(k_yz_inv_c<N, T, TIO>, kLdsLimit));
+                once = true;
+            }
+            KernelTimer kt("yz_inv", st);
+            hipLaunchKernelGGL((k_yz_inv_c<N, T, TIO>), grid, dim3(256), lds, st, static_cast<const cx<TIO> *>(psi),
+                               kd, ba, tw, static_cast<cx<T> *>(slab), P.nslab, bpw, P.max_rows, Cc);
+            return check_launch("yz_inv_c");
+        }
+        static bool once = false;
+        if (!once) {
+            APW_TRY(allow_lds(k_yz_fwd_c<N, T, TIO>, kLdsLimit));
+            once = true;
+        }
+        KernelTimer kt("yz_fwd", st);
+        hipLaunchKernelGGL((k_yz_fwd_c<N, T, TIO>), grid, dim3(256), lds, st, static_cast<const cx<T> *>(slab), P.nslab,
+                           kd, ba, tw, static_cast<const cx<TIO> *>(psi), static_cast<cx<TIO> *>(hpsi),
+                           1.0 / (double)P.N, bpw, P.max_rows, Cc);
+        return check_launch("yz_fwd_c");
+    }
     if (inverse) {
         static bool once = false;
         if (!once) {
-            APW_TRY(allow_lds(k_yz_inv<N, T, TIO>, lds));
+            APW_TRY(allow_lds(k_yz_inv<N, T, TIO>, lds_full));
             once = true;
         }
         KernelTimer kt("yz_inv", st);
-        hipLaunchKernelGGL((k_yz_inv<N, T, TIO>), grid, block, lds, st, static_cast<const cx<TIO> *>(psi),
-                           (int64_t)K.npw, K.pt_off, K.pt_g, K.pt_pos, K.row_off, K.row_list, tw,
-                           static_cast<cx<T> *>(slab), P.nslab, nbands, bpw);
+        hipLaunchKernelGGL((k_yz_inv<N, T, TIO>), grid, dim3(kYzThreads), lds_full, st,
+                           static_cast<const cx<TIO> *>(psi), kd, ba, tw, static_cast<cx<T> *>(slab), P.nslab, bpw);
         return check_launch("yz_inv");
     }
     static bool once = false;
     if (!once) {
-        APW_TRY(allow_lds(k_yz_fwd<N, T, TIO>, lds));
+        APW_TRY(allow_lds(k_yz_fwd<N, T, TIO>, lds_full));
         once = true;
     }
     KernelTimer kt("yz_fwd", st);
-    hipLaunchKernelGGL((k_yz_fwd<N, T, TIO>), grid, block, lds, st, static_cast<const cx<T> *>(slab), P.nslab,
-                       K.pt_off, K.pt_g, K.pt_pos, K.row_off, K.row_list, tw, K.kin,
-                       static_cast<const cx<TIO> *>(psi), static_cast<cx<TIO> *>(hpsi), (int64_t)K.npw,
-                       1.0 / (double)P.N, nbands, bpw);
+    hipLaunchKernelGGL((k_yz_fwd<N, T, TIO>), grid, dim3(kYzThreads), lds_full, st, static_cast<const cx<T> *>(slab),
+                       P.nslab, kd, ba, tw, static_cast<const cx<TIO> *>(psi), static_cast<cx<TIO> *>(hpsi),
+                       1.0 / (double)P.N, bpw);
     return check_launch("yz_fwd");
 }
 
@@ -353,11 +546,11 @@ int local_length_supported(int n) {
 }
 
 template <typename T, typename TIO>
-static int dispatch_yz(bool inverse, const Plan &P, const KTables &K, const void *psi, void *hpsi, void *slab,
-                       int nbands, hipStream_t st) {
+static int dispatch_yz(bool inverse, const Plan &P, int k0, int nkb, const BatchArgs &ba, const void *psi, void *hpsi,
+                       void *slab, hipStream_t st) {
     switch (P.N3) {
 #define APW_CASE(n) \
-    case n: return launch_yz<n, T, TIO>(inverse, P, K, psi, hpsi, slab, nbands, st);
+    case n: return launch_yz<n, T, TIO>(inverse, P, k0, nkb, ba, psi, hpsi, slab, st);
         APW_LENGTHS(APW_CASE)
 #undef APW_CASE
         default:
@@ -382,8 +575,8 @@ int local_supported(const Plan &P, int fft_prec) {
         return set_error(ABACUS_PW_EBAD_FFT_SIZE, "grid length without a transform");
     if (P.N2 != P.N3) return set_error(ABACUS_PW_EBAD_FFT_SIZE, "the plane transform needs N2 == N3");
     const size_t cb = fft_prec == 0 ? 16 : 8;
-    if ((size_t)(P.N3 * P.N3 + P.N3) * cb > kLdsLimit)
-        return set_error(ABACUS_PW_EBAD_FFT_SIZE, "grid plane too large for LDS at this precision");
+    const size_t need = ((size_t)P.max_rows * P.N3 + (size_t)P.N3 * 4 + P.N3) * cb + (size_t)P.N3 * 4;
+    if (need > kLdsLimit) return set_error(ABACUS_PW_EBAD_FFT_SIZE, "y-z plane rows do not fit in LDS at this precision");
     return ABACUS_PW_OK;
 }
 
@@ -410,12 +603,13 @@ static int launch_gradv(const Plan &P, const void *sx, const void *sy, int nband
     return check_launch("gradv_x");
 }
 
-int local_inverse_planes(const Plan &P, int kidx, int fft_prec, int io_prec, const void *psi, void *slab, int nbands,
-                         hipStream_t st) {
-    const KTables &K = P.k[kidx];
-    if (fft_prec == 0) return dispatch_yz<double, double>(true, P, K, psi, nullptr, slab, nbands, st);
-    if (io_prec == 1) return dispatch_yz<float, float>(true, P, K, psi, nullptr, slab, nbands, st);
-    return dispatch_yz<float, double>(true, P, K, psi, nullptr, slab, nbands, st);
+int local_inverse_planes(const Plan &P, int k0, int k1, int nb, int b0, int bbt, int fft_prec, int io_prec,
+                         const void *psi, void *slab, hipStream_t st) {
+    const BatchArgs ba{nb, P.pw_off[k0], b0, bbt};
+    const int nkb = k1 - k0;
+    if (fft_prec == 0) return dispatch_yz<double, double>(true, P, k0, nkb, ba, psi, nullptr, slab, st);
+    if (io_prec == 1) return dispatch_yz<float, float>(true, P, k0, nkb, ba, psi, nullptr, slab, st);
+    return dispatch_yz<float, double>(true, P, k0, nkb, ba, psi, nullptr, slab, st);
 }
 
 int local_gradv_accumulate(const Plan &P, int fft_prec, const void *slab_x, const void *slab_y, int nbands,
@@ -440,26 +634,24 @@ int local_gradv_finish(const Plan &P, const double *part, int G, double *grad_v,
     return check_launch("gradv_reduce");
 }
 
-int local_term(const Plan &P, int kidx, int fft_prec, int io_prec, const void *vloc, const void *psi, void *hpsi,
-               int nb, void *slab, int band_batch, hipStream_t st) {
-    const KTables &K = P.k[kidx];
-    const size_t ib = io_prec == 0 ? 16 : 8;
+int local_term(const Plan &P, int k0, int k1, int fft_prec, int io_prec, const void *vloc, const void *psi,
+               void *hpsi, int nb, void *slab, int band_batch, hipStream_t st) {
+    const int nkb = k1 - k0;
     for (int b0 = 0; b0 < nb; b0 += band_batch) {
-        const int nbb = nb - b0 < band_batch ? nb - b0 : band_batch;
-        const char *x = static_cast<const char *>(psi) + (size_t)b0 * K.npw * ib;
-        char *y = static_cast<char *>(hpsi) + (size_t)b0 * K.npw * ib;
+        const BatchArgs ba{nb, P.pw_off[k0], b0, std::min(band_batch, nb - b0)};
+        const int nv = nkb * ba.bbt;   // (k, band) planes sets in this batch
         if (fft_prec == 0) {
-            APW_TRY((dispatch_yz<double, double>(true, P, K, x, nullptr, slab, nbb, st)));
-            APW_TRY((dispatch_x<double>(P, vloc, slab, nbb, st)));
-            APW_TRY((dispatch_yz<double, double>(false, P, K, x, y, slab, nbb, st)));
+            APW_TRY((dispatch_yz<double, double>(true, P, k0, nkb, ba, psi, nullptr, slab, st)));
+            APW_TRY((dispatch_x<double>(P, vloc, slab, nv, st)));
+            APW_TRY((dispatch_yz<double, double>(false, P, k0, nkb, ba, psi, hpsi, slab, st)));
         } else if (io_prec == 1) {
-            APW_TRY((dispatch_yz<float, float>(true, P, K, x, nullptr, slab, nbb, st)));
-            APW_TRY((dispatch_x<float>(P, vloc, slab, nbb, st)));
-            APW_TRY((dispatch_yz<float, float>(false, P, K, x, y, slab, nbb, st)));
+            APW_TRY((dispatch_yz<float, float>(true, P, k0, nkb, ba, psi, nullptr, slab, st)));
+            APW_TRY((dispatch_x<float>(P, vloc, slab, nv, st)));
+            APW_TRY((dispatch_yz<float, float>(false, P, k0, nkb, ba, psi, hpsi, slab, st)));
         } else {
-            APW_TRY((dispatch_yz<float, double>(true, P, K, x, nullptr, slab, nbb, st)));
-            APW_TRY((dispatch_x<float>(P, vloc, slab, nbb, st)));
-            APW_TRY((dispatch_yz<float, double>(false, P, K, x, y, slab, nbb, st)));
+            APW_TRY((dispatch_yz<float, double>(true, P, k0, nkb, ba, psi, nullptr, slab, st)));
+            APW_TRY((dispatch_x<float>(P, vloc, slab, nv, st)));
+            APW_TRY((dispatch_yz<float, double>(false, P, k0, nkb, ba, psi, hpsi, slab, st)));
         }
     }
     return ABACUS_PW_OK;

@@ -12,15 +12,17 @@ int local_supported(const Plan &P, int fft_prec);
 // Slab work space for nbands bands.
 size_t local_slab_bytes(const Plan &P, int fft_prec, int nbands);
 
-// hpsi = |k+G|^2 psi + (V psi) for nb bands of k-point kidx ([nb][npw_k] blocks).
-// fft_prec: 0 FP64, 1 FP32 transforms. io_prec: 0 complex128, 1 complex64 psi/hpsi.
-// vloc: float64 grid for fft_prec 0, float32 for 1. slab: local_slab_bytes(band_batch).
-int local_term(const Plan &P, int kidx, int fft_prec, int io_prec, const void *vloc, const void *psi, void *hpsi,
-               int nb, void *slab, int band_batch, hipStream_t st);
+// hpsi = |k+G|^2 psi + (V psi) for nb bands at the k-points [k0, k1): psi and hpsi start at
+// k0's [nb][npw_k] block, k blocks back to back. Each band batch runs every k-point in one
+// launch per pass. fft_prec: 0 FP64, 1 FP32 transforms. io_prec: 0 complex128, 1 complex64.
+// vloc: float64 grid for fft_prec 0, float32 for 1. slab: local_slab_bytes((k1-k0) band_batch).
+int local_term(const Plan &P, int k0, int k1, int fft_prec, int io_prec, const void *vloc, const void *psi,
+               void *hpsi, int nb, void *slab, int band_batch, hipStream_t st);
 
-// Inverse y-z transforms of nbands bands of k-point kidx into slab planes (first pass of local_term).
-int local_inverse_planes(const Plan &P, int kidx, int fft_prec, int io_prec, const void *psi, void *slab, int nbands,
-                         hipStream_t st);
+// Inverse y-z transforms of bands [b0, b0+bbt) at the k-points [k0, k1) into slab planes
+// (virtual band (k - k0) * bbt + b); psi starts at k0's block of nb bands.
+int local_inverse_planes(const Plan &P, int k0, int k1, int nb, int b0, int bbt, int fft_prec, int io_prec,
+                         const void *psi, void *slab, hipStream_t st);
 // part[g] (+)= sum over bands b = g (mod G) of Re(conj(gamma_b(r)) psi_b(r)), from the slab planes of
 // psi (slab_x) and dY (slab_y); part is [G][N1][N2][N3]; first != 0 overwrites.
 int local_gradv_accumulate(const Plan &P, int fft_prec, const void *slab_x, const void *slab_y, int nbands,

@@ -21,6 +21,7 @@ int g_band_batch = 0;
 int g_splitk_chunk = 0;
 int g_yz_bands = 0;
 int g_x_bands = 0;
+int g_yz_mode = 0;
 
 DeviceBuffer::~DeviceBuffer() {
     if (ptr) (void)hipFree(ptr);
@@ -246,6 +247,7 @@ int build_plan(const abacus_pw_problem *p, Plan &P) {
             std::sort(rows.begin(), rows.end());
             rows.erase(std::unique(rows.begin(), rows.end()), rows.end());
             row_list.insert(row_list.end(), rows.begin(), rows.end());
+            P.max_rows = std::max(P.max_rows, (int)rows.size());
             row_off[s + 1] = (int)row_list.size();
         }
         std::vector<double> kin(npw);
@@ -321,6 +323,16 @@ int build_plan(const abacus_pw_problem *p, Plan &P) {
         K.row_list = reinterpret_cast<const int *>(at(koffs[k].row_list));
         K.kin = reinterpret_cast<const double *>(at(koffs[k].kin));
         K.kin32 = reinterpret_cast<const float *>(at(koffs[k].kin32));
+    }
+    {
+        std::vector<KDesc> kd(p->nk);
+        for (int k = 0; k < p->nk; ++k) {
+            const KTables &K = P.k[k];
+            kd[k] = KDesc{K.pt_off, K.pt_g, K.pt_pos, K.row_off, K.row_list, K.kin, K.pw_off, K.npw, 0};
+        }
+        APW_TRY(P.kdesc_buf.ensure(sizeof(KDesc) * kd.size()));
+        APW_HIP(hipMemcpy(P.kdesc_buf.ptr, kd.data(), sizeof(KDesc) * kd.size(), hipMemcpyHostToDevice));
+        P.kdesc = P.kdesc_buf.as<const KDesc>();
     }
     P.row_to_slab = reinterpret_cast<const int *>(at(o_r2s));
     for (int ax = 0; ax < 3; ++ax) {

@@ -30,6 +30,20 @@ struct KTables {
     const float *kin32 = nullptr;
 };
 
+// The same tables as device-resident descriptors, one per k-point, so a single
+// launch can cover several k-points.
+struct KDesc {
+    const int *pt_off;
+    const int *pt_g;
+    const int *pt_pos;
+    const int *row_off;
+    const int *row_list;
+    const double *kin;
+    int64_t pw_off;
+    int npw;
+    int pad;
+};
+
 struct DeviceBuffer {
     void *ptr = nullptr;
     size_t bytes = 0;
@@ -45,6 +59,7 @@ struct Plan {
     int N1 = 0, N2 = 0, N3 = 0;
     int64_t N = 0;
     int nslab = 0, m1min = 0;
+    int max_rows = 0;              // most z-column rows in any plane of any k-point
     int nk = 0;
     std::vector<int> npw;
     std::vector<int64_t> pw_off;   // [nk+1]
@@ -56,6 +71,8 @@ struct Plan {
 
     // device tables
     DeviceBuffer tables;          // all int/double geometry tables, one allocation
+    DeviceBuffer kdesc_buf;       // KDesc[nk]
+    const KDesc *kdesc = nullptr;
     const int *row_to_slab = nullptr;     // [N1]: slab index of LDS row perm1(i1), or -1
     const void *tw64[3] = {nullptr, nullptr, nullptr};   // per axis, cx<double>[N_i]
     const void *tw32[3] = {nullptr, nullptr, nullptr};   // per axis, cx<float>[N_i]
@@ -89,6 +106,7 @@ extern int g_band_batch;    // bands per local-term batch
 extern int g_splitk_chunk;  // K chunk of the split-K projection GEMM
 extern int g_yz_bands;      // bands per y-z plane work-group
 extern int g_x_bands;       // bands per x-pass work-group
+extern int g_yz_mode;       // plane kernels: 0 auto, 1 full plane in LDS, 2 compact rows
 
 // Looks up or builds the plan for a problem (validates it on build).
 int get_plan(const abacus_pw_problem *p, Plan **out);

@@ -107,6 +107,20 @@ def test_c2_mixed_fp32(c2, c2_ref):
     assert rel(y, c2_ref) < 1e-5
 
 
+def test_c2_mixed_bf16(c2, c2_ref):
+    """BF16 projector operands (8-bit mantissa, rounding 2^-9 relative) with FP32 accumulation:
+    the nonlocal term carries ~1e-3 relative error; bound 2e-2 on it and on the whole of H psi."""
+    y = gpu_apply(c2, prec=B().MIXED_BF16)
+    assert rel(y, c2_ref) < 2e-2
+    q = dataclasses.replace(c2, vloc=np.zeros_like(c2.vloc))
+    kin = oracle.kinetic(q, 0)
+    nl_ref = oracle.apply_h(q, q.psi).reshape(q.nb, -1) - kin[None, :] * q.psi.reshape(q.nb, -1)
+    nl = gpu_apply(q, prec=B().MIXED_BF16).reshape(q.nb, -1) - kin[None, :] * q.psi.reshape(q.nb, -1)
+    e = rel(nl, nl_ref)
+    print(f"bf16 nonlocal relative error {e:.3e}", flush=True)
+    assert e < 2e-2
+
+
 def test_c1_fp32(c1):
     y = gpu_apply(c1, prec=B().FP32)
     assert rel(y, oracle.apply_h(c1, c1.psi)) < 1e-5
@@ -150,13 +164,35 @@ def test_c5_sampled_bands_all_kpoints():
         assert rel(yk[take], ref) < 1e-12
 
 
-def test_unsupported_plane_reports_error():
+def test_large_plane_fp64_uses_compact_rows():
+    """A 128^3 FP64 plane (262 KB) does not fit LDS: the compact-row kernels run it."""
+    p = W.make_problem(W.tiny_config(fft=128, ecut=10.0, a=8.0, nb=2, natom=1))
+    y = gpu_apply(p)
+    assert rel(y, oracle.apply_h(p, p.psi)) < 1e-12
+    y32 = gpu_apply(p, prec=B().FP32)
+    assert rel(y32, oracle.apply_h(p, p.psi)) < 1e-5
+
+
+@pytest.mark.parametrize("mode", [1, 2])
+def test_plane_modes_and_tuning_agree(c2, c2_ref, mode):
+    """Whole-plane and compact-row kernels, odd band groups and a small batch: same H psi."""
     b = B()
-    p = W.make_problem(W.tiny_config(fft=128, ecut=10.0, a=8.0, nb=1, natom=1))
-    dp = b.DeviceProblem(p)
-    x = torch.from_numpy(p.psi).cuda()
-    with pytest.raises(b.AbacusPwError) as e:
-        b.apply_h(dp, x)
-    assert e.value.name == "EBAD_FFT_SIZE"
-    y = b.apply_h(dp, x.to(torch.complex64), b.FP32)   # the FP32 plane fits
-    assert rel(y.cpu().numpy(), oracle.apply_h(p, p.psi)) < 1e-5
+    try:
+        b.set_tuning(band_batch=24, splitk_chunk=512, yz_bands=3, x_bands=5, yz_mode=mode)
+        y = gpu_apply(c2)
+        assert rel(y, c2_ref) < 1e-12
+        y32 = gpu_apply(c2, prec=b.FP32)
+        assert rel(y32, c2_ref) < 1e-5
+    finally:
+        b.set_tuning()
+
+
+@pytest.mark.parametrize("cfg", [
+    dict(a=30.0, ecut=40.0, fft=120, kfrac=((0.5, 0.5, 0.5),), natom=12, nb=3, seed=3),
+    dict(a=30.0, ecut=50.0, fft=128, natom=6, lmax=2, dfull=True, nb=2, seed=4),
+])
+def test_c3_c4_geometry_fp64(cfg):
+    """The 120^3 (R point) and 128^3 grids of the two largest workloads, few bands and atoms, FP64."""
+    p = W.make_problem(W.tiny_config(**cfg))
+    y = gpu_apply(p)
+    assert rel(y, oracle.apply_h(p, p.psi)) < 1e-12

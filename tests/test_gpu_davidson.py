@@ -138,6 +138,15 @@ def test_mixed_fp32_refines_to_fp64():
     check_vectors(p, psi, emx, 16, 1.5e-10)
 
 
+def test_mixed_bf16_refines_to_fp64():
+    p = W.make_problem("C1")
+    e64, _, _, _, st64 = gpu_davidson(p, 1e-10, 400)
+    ebf, psi, res, its, st = gpu_davidson(p, 1e-10, 400, prec=B().MIXED_BF16)
+    assert st == 0 and st64 == 0
+    np.testing.assert_allclose(ebf, e64, atol=1e-11)
+    check_vectors(p, psi, ebf, 16, 1.5e-10)
+
+
 def test_rejects_bad_sizes():
     b = B()
     p = W.make_problem(W.tiny_config(fft=8, ecut=5.0, nb=2))
