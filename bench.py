@@ -46,6 +46,7 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-davidson", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--no-batched", action="store_true")
     return ap.parse_args()
 
 
@@ -239,10 +240,70 @@ def main():
 
     if not args.no_davidson:
         out["davidson"] = davidson_times(B, W, dev)
+    if not args.no_batched:
+        out["batched_kpoints"] = batched_times(B, W, dev, max(5, args.steps // 4))
 
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(prob)
     print(json.dumps(out), flush=True)
+
+
+def batched_times(B, W, dev, steps):
+    """H psi over four uneven k-points (Gamma, X, M, R; 96^3; 256 bands each; 512 projectors).
+
+    Plain FP64 with one call per k-point, against every k-point in one call
+    (one launch per pass per band batch), that call replayed from a HIP graph,
+    and the FP32 and MIXED_BF16 forms of the replayed call. Rates are
+    band-applies per second over all k-points.
+    """
+    import torch
+    prob = W.make_problem("C5")
+    nb, nk = prob.nb, prob.nk
+    B.set_tuning()
+    dp = B.DeviceProblem(prob, device=dev)
+    x = torch.from_numpy(prob.psi).to(dev)
+    x32 = x.to(torch.complex64)
+    off = prob.pw_offsets
+    subs = []
+    for k in range(nk):
+        sub = prob.single_k(k)
+        beta_k = dp.beta[prob.nproj * off[k]: prob.nproj * off[k + 1]]
+        dk = B.DeviceProblem(sub, device=dev, vloc=dp.vloc, dmat=dp.dmat, beta=beta_k)
+        subs.append((dk, x[nb * off[k]: nb * off[k + 1]], torch.empty(nb * (off[k + 1] - off[k]),
+                                                                        dtype=x.dtype, device=dev)))
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        for _ in range(steps):
+            fn()
+        b.record()
+        torch.cuda.synchronize()
+        return a.elapsed_time(b) / steps
+
+    res = {"workload": "C5: cubic a=24 bohr, ecutwfc=35 Ry, 96^3, k = G, X, M, R (npw " +
+                       "/".join(str(int(n)) for n in prob.npw) + "), 256 bands each, 128 atoms x 4 projectors"}
+    t_perk = timed(lambda: [B.apply_h(dk, xk, out=yk) for dk, xk, yk in subs])
+    y = torch.empty_like(x)
+    t_batch = timed(lambda: B.apply_h(dp, x, out=y))
+    out = {}
+    for name, prec, xx in (("fp64", B.FP64, x), ("fp32", B.FP32, x32), ("mixed_bf16", B.MIXED_BF16, x)):
+        yy = torch.empty_like(xx)
+        B.apply_h(dp, xx, prec, out=yy)
+        torch.cuda.synchronize()
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            B.apply_h(dp, xx, prec, out=yy)
+        out[name] = timed(g.replay)
+    tot = nk * nb
+    res["fp64_per_kpoint_calls"] = {"ms": t_perk, "band_applies_per_s": tot / (t_perk * 1e-3)}
+    res["fp64_batched"] = {"ms": t_batch, "band_applies_per_s": tot / (t_batch * 1e-3)}
+    for name, ms in out.items():
+        res[name + "_batched_graph"] = {"ms": ms, "band_applies_per_s": tot / (ms * 1e-3),
+                                        "speedup_vs_fp64_per_kpoint": t_perk / ms}
+    return res
 
 
 def davidson_times(B, W, dev):

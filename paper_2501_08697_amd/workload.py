@@ -113,6 +113,18 @@ class Problem:
         off = self.pw_offsets
         return self.miller[off[k]: off[k + 1]]
 
+    def single_k(self, k: int) -> "Problem":
+        """The problem restricted to k-point k (views of the same arrays)."""
+        off = self.pw_offsets
+        sl = slice(self.nb * off[k], self.nb * off[k + 1])
+        return Problem(
+            lattice=self.lattice, fft=self.fft, ecut=self.ecut, kpts=self.kpts[k:k + 1], npw=self.npw[k:k + 1],
+            miller=self.miller[off[k]:off[k + 1]], vloc=self.vloc, nproj=self.nproj, natom=self.natom,
+            proj_atom_offset=self.proj_atom_offset, beta=self.beta[self.nproj * off[k]: self.nproj * off[k + 1]],
+            dmat=self.dmat, nb=self.nb, psi=self.psi[sl],
+            occ=None if self.occ is None else self.occ[k:k + 1], dy=None if self.dy is None else self.dy[sl],
+            tau=self.tau, depth=self.depth, name=f"{self.name}[k{k}]")
+
     def dblock(self, atom: int) -> np.ndarray:
         n = int(self.proj_atom_offset[atom + 1] - self.proj_atom_offset[atom])
         o = int(sum((self.proj_atom_offset[i + 1] - self.proj_atom_offset[i]) ** 2 for i in range(atom)))
