@@ -137,7 +137,7 @@ def main():
     dev = torch.device("cuda:0")
     prob = W.make_problem(WORKLOAD)
     nb = prob.nb
-    dp = B.DeviceProblem(prob, device=dev)
+    dp = B.DeviceProblem(prob, device=dev, static=True)   # operator data constant for the whole run
     x64 = torch.from_numpy(prob.psi).to(dev)
     x32 = x64.to(torch.complex64)
     y64 = torch.empty_like(x64)
@@ -260,7 +260,7 @@ def batched_times(B, W, dev, steps):
     prob = W.make_problem("C5")
     nb, nk = prob.nb, prob.nk
     B.set_tuning()
-    dp = B.DeviceProblem(prob, device=dev)
+    dp = B.DeviceProblem(prob, device=dev, static=True)
     x = torch.from_numpy(prob.psi).to(dev)
     x32 = x.to(torch.complex64)
     off = prob.pw_offsets
@@ -268,7 +268,7 @@ def batched_times(B, W, dev, steps):
     for k in range(nk):
         sub = prob.single_k(k)
         beta_k = dp.beta[prob.nproj * off[k]: prob.nproj * off[k + 1]]
-        dk = B.DeviceProblem(sub, device=dev, vloc=dp.vloc, dmat=dp.dmat, beta=beta_k)
+        dk = B.DeviceProblem(sub, device=dev, vloc=dp.vloc, dmat=dp.dmat, beta=beta_k, static=True)
         subs.append((dk, x[nb * off[k]: nb * off[k + 1]], torch.empty(nb * (off[k + 1] - off[k]),
                                                                         dtype=x.dtype, device=dev)))
 

@@ -90,9 +90,14 @@ class DeviceProblem:
 
     Host arrays (lattice, kpts, npw, miller, proj_atom_offset) are kept as
     contiguous numpy buffers; vloc, beta and dmat as torch device tensors.
+
+    static=True sets ABACUS_PW_STATIC_OPERATOR: the library may then keep its
+    reduced-precision copies of V and beta between calls, keyed by pointer. Only
+    use it while these tensors stay alive and unchanged: a freed tensor's address
+    is soon reused by torch's allocator for different data.
     """
 
-    def __init__(self, prob, device="cuda", vloc=None, dmat=None, beta=None, static=True):
+    def __init__(self, prob, device="cuda", vloc=None, dmat=None, beta=None, static=False):
         import torch
         self.prob = prob
         self.nk = int(len(prob.npw))

@@ -31,7 +31,7 @@ def test_graph_replay_is_bitwise_eager(prec):
     b = B()
     p = multi_k()
     print(f"[graph] fft={p.fft} npw={list(p.npw)} nb={p.nb} prec={prec}", flush=True)
-    dp = b.DeviceProblem(p)
+    dp = b.DeviceProblem(p, static=True)   # kept alive and unchanged through the replays
     x = torch.from_numpy(p.psi).cuda()
     if prec == b.FP32:
         x = x.to(torch.complex64)
