@@ -47,6 +47,8 @@ def parse():
     ap.add_argument("--no-davidson", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--traffic-probe", action="store_true",
+                    help="run a plain 256 MiB copy and a few H psi steps only (for counter collection)")
     return ap.parse_args()
 
 
@@ -148,6 +150,18 @@ def main():
         for _ in range(steps):
             B.apply_h(dp, x, prec, out=y)
 
+    if args.traffic_probe:
+        # calibration: one plain device copy of a known size, then the FP64 H psi with default tuning
+        n = 256 << 20
+        src = torch.ones(n // 8, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        run(B.FP64, x64, y64, max(1, args.steps))
+        torch.cuda.synchronize()
+        print(json.dumps({"traffic_probe": True, "copy_bytes": n, "steps": max(1, args.steps)}), flush=True)
+        return
+
     # warm-up (builds the plan, allocates work space), then the launch-shape autotuner
     run(B.FP64, x64, y64, args.warmup)
     run(B.FP32, x32, y32, args.warmup)
@@ -218,12 +232,13 @@ def main():
 
     out = {
         "metric": "Hψ band-applies/s, Davidson time/k-point vs plain FP64; % HBM & MFMA peak",
-        "value": nb / (ms64 * 1e-3),
+        "value": nb / (ms64_clean * 1e-3),
         "unit": "band-applies/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": ms64,
+        "ms_per_step": ms64_clean,
+        "ms_per_step_with_kernel_events": ms64,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -232,7 +247,6 @@ def main():
         "config": {"workload": f"{WORKLOAD}: {WORKLOAD_DESC}", "bands": nb, "npw": int(prob.npw[0]),
                    "fft": list(prob.fft), "nproj": prob.nproj, "kpoints": prob.nk},
         "roofline": roof,
-        "fp64_ms_per_step_without_kernel_events": ms64_clean,
         "fp32": {"ms_per_step": ms32, "band_applies_per_s": nb / (ms32 * 1e-3), "speedup_vs_fp64": ms64_clean / ms32},
         "kernels": rows,
         "tuning": tuning,

@@ -24,6 +24,8 @@ namespace apw {
 
 template <typename T> __device__ __forceinline__ cx<T> czero() { return cx<T>{T(0), T(0)}; }
 
+int lds_split_host(int n, int *a, int *b);
+
 // A band batch spread over the k-points [k0, k0 + nk) of a call: at every k the
 // bands [b0, b0 + bbt) of that k's [nb_total][npw_k] block; off0 = pw_off[k0].
 struct BatchArgs {
@@ -103,66 +105,97 @@ __global__ __launch_bounds__(kYzThreads) void k_yz_inv(const cx<TIN> *__restrict
     }
 }
 
-// One work-group per (j2, a tile of T3 consecutive j3 columns, a group of bands).
-// V of the tile is read once into registers and reused for every band of the
-// group; the next band's slab rows are fetched while the current one transforms.
+// One work-group per (j2, a tile of T3 consecutive j3 columns, a group of bands):
+// inverse x transform, x V(r), forward x transform, with N1 = A B split as in
+// lds_fft. Per band and column the work is three thread phases:
+//   I  task (c, ka): the B slab values of slots B ka + kb come straight from
+//      HBM; inverse DFT_B, twiddle, to LDS.
+//   F  task (c, jb): the A values of slots jb + B ka from LDS; inverse DFT_A
+//      gives x(j1) at j1 = jb + B ja; times V(j1, j2, j3) (held in registers
+//      for the whole band group); forward DFT_A on the same values; twiddle;
+//      back to the same LDS slots.
+//   O  task (c, ka): slots B ka + jb from LDS; forward DFT_B; the slots that
+//      belong to the slab go straight to HBM.
+// So each element crosses LDS twice per band (once per transpose) and there
+// are three barriers per band. The next band's phase-I values are fetched
+// while the current band finishes. The tile width keeps w3 B <= 256, so every
+// thread owns at most one task per phase.
 template <int N1, typename T, typename TV>
 __global__ __launch_bounds__(256) void k_xpass(cx<T> *__restrict__ slab, int nslab, int N2, int N3, int T3, int nt3,
                                                int nbands, int bpw, const int *__restrict__ row_to_slab,
                                                const TV *__restrict__ vloc, const cx<T> *__restrict__ tw_g) {
-    constexpr int MAXV = (N1 * kMaxT3 + 255) / 256;
+    constexpr int A = LdsSplit<N1>::A, B = LdsSplit<N1>::B;
     extern __shared__ __align__(16) unsigned char smem[];
-    cx<T> *tile = reinterpret_cast<cx<T> *>(smem);
+    cx<T> *tile = reinterpret_cast<cx<T> *>(smem);       // [N1 slots][T3]
     cx<T> *tw = tile + N1 * T3;
+    int *r2s = reinterpret_cast<int *>(tw + N1);
     const int j2 = blockIdx.x / nt3, c0 = (blockIdx.x - j2 * nt3) * T3;
     const int w3 = min(T3, N3 - c0);
     const int b0 = blockIdx.y * bpw, b1 = min(nbands, b0 + bpw);
-    const int tid = threadIdx.x, nthr = blockDim.x;
+    const int tid = threadIdx.x;
     const int64_t plane = (int64_t)N2 * N3;
     const int64_t bstride = (int64_t)nslab * plane;
-    const int ntile = N1 * w3;
-    for (int i = tid; i < N1; i += nthr) tw[i] = tw_g[i];
-    T vreg[MAXV];
-    int64_t src[MAXV];      // offset of this thread's element inside a band's slab, or -1
-    cx<T> pre[MAXV];
-    cx<T> *base = slab + (int64_t)j2 * N3 + c0;
-#pragma unroll
-    for (int q = 0; q < MAXV; ++q) {
-        const int i = tid + q * 256;
-        vreg[q] = T(0);
-        src[q] = -1;
-        if (i < ntile) {
-            const int r = i / w3, c = i - r * w3;
-            vreg[q] = static_cast<T>(vloc[(int64_t)r * plane + (int64_t)j2 * N3 + c0 + c]);
-            const int sl = row_to_slab[r];
-            if (sl >= 0) src[q] = sl * plane + c;
-        }
-        pre[q] = src[q] >= 0 ? base[b0 * bstride + src[q]] : czero<T>();
+    for (int i = tid; i < N1; i += blockDim.x) {
+        tw[i] = tw_g[i];
+        r2s[i] = row_to_slab[i];
     }
-    for (int b = b0; b < b1; ++b) {
+    __syncthreads();
+    // task of this thread in the (c, ka) phases and in the (c, jb) phase
+    const int c = w3 > 0 ? tid % w3 : 0;
+    const int ka = tid / w3;           // valid when tid < w3 * A
+    const int jb = tid / w3;           // valid when tid < w3 * B
+    const bool has_ka = tid < w3 * A, has_jb = tid < w3 * B;
+    cx<T> *base = slab + (int64_t)j2 * N3 + c0 + c;
+    T vr[A];
+    int64_t src[B];
 #pragma unroll
-        for (int q = 0; q < MAXV; ++q) {
-            const int i = tid + q * 256;
-            if (i < ntile) tile[i] = pre[q];
+    for (int ja = 0; ja < A; ++ja)
+        vr[ja] = has_jb ? static_cast<T>(vloc[(int64_t)(jb + B * ja) * plane + (int64_t)j2 * N3 + c0 + c]) : T(0);
+#pragma unroll
+    for (int kb = 0; kb < B; ++kb) {
+        const int sl = has_ka ? r2s[B * ka + kb] : -1;
+        src[kb] = sl >= 0 ? sl * plane : -1;
+    }
+    cx<T> pre[B];
+#pragma unroll
+    for (int kb = 0; kb < B; ++kb) pre[kb] = (has_ka && src[kb] >= 0) ? base[b0 * bstride + src[kb]] : czero<T>();
+    for (int b = b0; b < b1; ++b) {
+        if (has_ka) {
+            cx<T> z[B];
+#pragma unroll
+            for (int kb = 0; kb < B; ++kb) z[kb] = pre[kb];
+            RegDft<B, +1, T>::run(z);
+            tile[(B * ka) * T3 + c] = z[0];
+#pragma unroll
+            for (int q = 1; q < B; ++q) tile[(B * ka + q) * T3 + c] = cmul(z[q], tw[q * A + ka]);
+        }
+        __syncthreads();
+        if (has_jb) {
+            cx<T> a[A];
+#pragma unroll
+            for (int q = 0; q < A; ++q) a[q] = tile[(jb + B * q) * T3 + c];
+            RegDft<A, +1, T>::run(a);
+#pragma unroll
+            for (int q = 0; q < A; ++q) a[q] = a[q] * vr[q];
+            RegDft<A, -1, T>::run(a);
+            tile[jb * T3 + c] = a[0];
+#pragma unroll
+            for (int q = 1; q < A; ++q) tile[(jb + B * q) * T3 + c] = cmulc(a[q], tw[jb * A + q]);
         }
         __syncthreads();
         if (b + 1 < b1) {
 #pragma unroll
-            for (int q = 0; q < MAXV; ++q)
-                if (src[q] >= 0) pre[q] = base[(b + 1) * bstride + src[q]];
+            for (int kb = 0; kb < B; ++kb)
+                if (has_ka && src[kb] >= 0) pre[kb] = base[(b + 1) * bstride + src[kb]];
         }
-        lds_fft<N1, +1, true>(tile, w3, [](int l) { return l; }, w3, tw);
+        if (has_ka) {
+            cx<T> z[B];
 #pragma unroll
-        for (int q = 0; q < MAXV; ++q) {
-            const int i = tid + q * 256;
-            if (i < ntile) tile[i] = tile[i] * vreg[q];
-        }
-        __syncthreads();
-        lds_fft<N1, -1, true>(tile, w3, [](int l) { return l; }, w3, tw);
+            for (int q = 0; q < B; ++q) z[q] = tile[(B * ka + q) * T3 + c];
+            RegDft<B, -1, T>::run(z);
 #pragma unroll
-        for (int q = 0; q < MAXV; ++q) {
-            const int i = tid + q * 256;
-            if (src[q] >= 0) base[b * bstride + src[q]] = tile[i];
+            for (int kb = 0; kb < B; ++kb)
+                if (src[kb] >= 0) base[b * bstride + src[kb]] = z[kb];
         }
         __syncthreads();
     }
@@ -505,17 +538,21 @@ static int launch_yz(bool inverse, const Plan &P, int k0, int nkb, const BatchAr
     return check_launch("yz_fwd");
 }
 
-// j3 tile width of the x pass: the widest divisor of N3 in [8, 32], else 32 with a ragged last tile.
-static int xpass_tile(int n3) {
-    for (int t = kMaxT3; t >= 8; --t)
+// j3 tile width of the x pass: the widest divisor of N3 that keeps T3 * B <= 256
+// (one task per thread and phase) and T3 <= 32; else that bound with a ragged tile.
+static int xpass_tile(int n1, int n3) {
+    int a, b;
+    lds_split_host(n1, &a, &b);
+    const int cap = std::min(kMaxT3, 256 / b);
+    for (int t = cap; t >= 4; --t)
         if (n3 % t == 0) return t;
-    return n3 < kMaxT3 ? n3 : kMaxT3;
+    return std::min(cap, n3);
 }
 
 template <int N1, typename T>
 static int launch_x(const Plan &P, const void *vloc, void *slab, int nbands, hipStream_t st) {
-    const int T3 = xpass_tile(P.N3), nt3 = ceil_div(P.N3, T3);
-    const size_t lds = (size_t)(N1 * T3 + N1) * sizeof(cx<T>);
+    const int T3 = xpass_tile(N1, P.N3), nt3 = ceil_div(P.N3, T3);
+    const size_t lds = (size_t)(N1 * T3 + N1) * sizeof(cx<T>) + (size_t)N1 * sizeof(int);
     static bool once = false;
     if (!once) {
         APW_TRY(allow_lds(k_xpass<N1, T, T>, kLdsLimit));
@@ -588,7 +625,7 @@ size_t local_slab_bytes(const Plan &P, int fft_prec, int nbands) {
 template <int N1, typename T>
 static int launch_gradv(const Plan &P, const void *sx, const void *sy, int nbands, double *part, int G, int first,
                         hipStream_t st) {
-    const int T3 = xpass_tile(P.N3), nt3 = ceil_div(P.N3, T3);
+    const int T3 = std::min(xpass_tile(N1, P.N3), kMaxT3), nt3 = ceil_div(P.N3, T3);
     const size_t lds = (size_t)(N1 * T3 + N1) * sizeof(cx<T>);
     static bool once = false;
     if (!once) {
