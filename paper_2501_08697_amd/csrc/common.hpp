@@ -83,6 +83,25 @@ inline int check_launch(const char *what) {
 }
 
 inline int ceil_div(int a, int b) { return (a + b - 1) / b; }
+
+// MI355X dispatches consecutive work-groups round-robin over its 8 XCDs, each
+// with its own L2. xcd_block() maps the hardware block id of a 3-D grid to a
+// logical block id such that logically consecutive blocks run on the same XCD:
+// hardware id w runs on XCD w % 8 and takes logical id (w % 8) * (W / 8) + w / 8.
+// Blocks beyond the largest multiple of 8 keep their id. Kernels decode the
+// logical id with x fastest, so blocks that share operands (consecutive x)
+// share an L2.
+constexpr int kNumXcd = 8;
+__device__ __forceinline__ void xcd_block(int &bx, int &by, int &bz) {
+    const int gx = gridDim.x, gy = gridDim.y;
+    const int W = gx * gy * gridDim.z;
+    const int w = blockIdx.x + gx * (blockIdx.y + gy * blockIdx.z);
+    const int per = W / kNumXcd;
+    const int L = w < per * kNumXcd ? (w % kNumXcd) * per + w / kNumXcd : w;
+    bx = L % gx;
+    by = (L / gx) % gy;
+    bz = L / (gx * gy);
+}
 inline int64_t ceil_div64(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
 }  // namespace apw

@@ -50,7 +50,9 @@ __global__ __launch_bounds__(256) void k_gemm_cn_part(int M, int N, int K, int k
     __shared__ cx<T> As[TM][KP];
     __shared__ cx<T> Bs[TN][KP];
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-    const int i0 = blockIdx.x * TM, j0 = blockIdx.y * TN, s = blockIdx.z;
+    int bx, by, bz;
+    xcd_block(bx, by, bz);   // the tiles of one K chunk share an L2
+    const int i0 = bx * TM, j0 = by * TN, s = bz;
     const int kb = s * kchunk, ke = min(K, kb + kchunk);
     using AV = typename Acc<T>::V;
     AV cre[2][2], cim[2][2];
@@ -180,7 +182,9 @@ __global__ __launch_bounds__(256) void k_gemm_nn(int M, int G, int K, const cx<T
     __shared__ cx<T> As[TM][KP];
     __shared__ cx<T> Bs[KT][TN + 1];
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-    const int j0 = blockIdx.y * TM, g0 = blockIdx.x * TN;
+    int bx, by, bz;
+    xcd_block(bx, by, bz);   // the row tiles of one column block share an L2
+    const int j0 = bx * TM, g0 = by * TN;
     using AV = typename Acc<T>::V;
     AV cre[2][2], cim[2][2];
 #pragma unroll
@@ -358,7 +362,7 @@ template <typename T, typename TC>
 static int gemm_nn_t(int M, int G, int K, const void *A, int64_t lda, const void *B, int64_t ldb, void *C,
                      int64_t ldc, double alpha, double beta, hipStream_t st) {
     if (M <= 0 || G <= 0) return ABACUS_PW_OK;
-    dim3 grid(ceil_div(G, TN), ceil_div(M, TM));
+    dim3 grid(ceil_div(M, TM), ceil_div(G, TN));
     KernelTimer kt("gemm_nn", st);
     hipLaunchKernelGGL((k_gemm_nn<T, TC>), grid, dim3(256), 0, st, M, G, K, static_cast<const cx<T> *>(A), lda,
                        static_cast<const cx<T> *>(B), ldb, static_cast<cx<TC> *>(C), ldc, alpha, beta);

@@ -55,7 +55,9 @@ __global__ __launch_bounds__(256) void k_cn_bf16(int M, int N, int K, int kchunk
     __shared__ __align__(16) uint32_t As[BT][BKP];
     __shared__ __align__(16) uint32_t Bs[BT][BKP];
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-    const int i0 = blockIdx.x * BT, j0 = blockIdx.y * BT, s = blockIdx.z;
+    int bx, by, bz;
+    xcd_block(bx, by, bz);
+    const int i0 = bx * BT, j0 = by * BT, s = bz;
     const int kb = s * kchunk, ke = min(K, kb + kchunk);
     f4 cre[2][2], cim[2][2];
 #pragma unroll
@@ -116,7 +118,9 @@ __global__ __launch_bounds__(256) void k_nn_bf16(int M, int G, int K, const c32 
     __shared__ __align__(16) uint32_t As[BT][BKP];    // [j][i]
     __shared__ __align__(16) uint32_t Bt[BT][BKP];    // transposed: [g][i]
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-    const int j0 = blockIdx.y * BT, g0 = blockIdx.x * BT;
+    int bx, by, bz;
+    xcd_block(bx, by, bz);
+    const int j0 = bx * BT, g0 = by * BT;
     f4 cre[2][2], cim[2][2];
 #pragma unroll
     for (int a = 0; a < 2; ++a)
@@ -228,7 +232,7 @@ int proj_dapply_bf16(int M, int N, int K, const void *Bpk, int64_t ldb, const vo
 int gemm_nn_bf16_into_f64(int M, int G, int K, const void *A, int64_t lda, const void *Bpk, int64_t ldb, void *C,
                           int64_t ldc, hipStream_t st) {
     if (M <= 0 || G <= 0) return ABACUS_PW_OK;
-    dim3 grid(ceil_div(G, BT), ceil_div(M, BT));
+    dim3 grid(ceil_div(M, BT), ceil_div(G, BT));
     KernelTimer kt("gemm_nn_bf16", st);
     hipLaunchKernelGGL(k_nn_bf16, grid, dim3(256), 0, st, M, G, K, static_cast<const c32 *>(A), lda,
                        static_cast<const uint32_t *>(Bpk), ldb, static_cast<z64 *>(C), ldc);

@@ -36,11 +36,15 @@ struct BatchArgs {
 };
 
 // Block y index -> (k-point, band range inside the batch) for work-groups of bpw bands.
+// The planes of one band group are logically consecutive (x = plane), so the
+// XCD remap keeps them, and the gathers of that group's psi, on one L2.
 __device__ __forceinline__ void batch_block(const KDesc *kd, const BatchArgs &ba, int bpw, KDesc &D, int &k, int &lb0,
-                                            int &lb1) {
+                                            int &lb1, int &plane) {
+    int by, bz;
+    xcd_block(plane, by, bz);
     const int gpk = (ba.bbt + bpw - 1) / bpw;
-    k = blockIdx.y / gpk;
-    const int g = blockIdx.y - k * gpk;
+    k = by / gpk;
+    const int g = by - k * gpk;
     D = kd[k];
     lb0 = g * bpw;
     lb1 = min(ba.bbt, lb0 + bpw);
@@ -60,7 +64,8 @@ __global__ __launch_bounds__(kYzThreads) void k_yz_inv(const cx<TIN> *__restrict
                                                        cx<T> *__restrict__ slab, int nslab, int bpw) {
     KDesc D;
     int kk, b0, b1;
-    batch_block(kd, ba, bpw, D, kk, b0, b1);
+    int s;
+    batch_block(kd, ba, bpw, D, kk, b0, b1, s);
     const int *__restrict__ pt_off = D.pt_off, *__restrict__ pt_g = D.pt_g, *__restrict__ pt_pos = D.pt_pos;
     const int *__restrict__ row_off = D.row_off, *__restrict__ row_list = D.row_list;
     const cx<TIN> *psi = psi_all + ba.nb_total * (D.pw_off - ba.off0) + (int64_t)ba.b0 * D.npw;
@@ -70,7 +75,6 @@ __global__ __launch_bounds__(kYzThreads) void k_yz_inv(const cx<TIN> *__restrict
     extern __shared__ __align__(16) unsigned char smem[];
     cx<T> *plane = reinterpret_cast<cx<T> *>(smem);
     cx<T> *tw = plane + N * N;
-    const int s = blockIdx.x;
     const int tid = threadIdx.x, nthr = blockDim.x;
     for (int i = tid; i < N; i += nthr) tw[i] = tw_g[i];
     const int p0 = pt_off[s], p1 = pt_off[s + 1];
@@ -210,7 +214,8 @@ __global__ __launch_bounds__(kYzThreads) void k_yz_fwd(const cx<T> *__restrict__
                                                        cx<TIO> *__restrict__ hpsi_all, double inv_n, int bpw) {
     KDesc D;
     int kk, b0, b1;
-    batch_block(kd, ba, bpw, D, kk, b0, b1);
+    int s;
+    batch_block(kd, ba, bpw, D, kk, b0, b1, s);
     const int *__restrict__ pt_off = D.pt_off, *__restrict__ pt_g = D.pt_g, *__restrict__ pt_pos = D.pt_pos;
     const int *__restrict__ row_off = D.row_off, *__restrict__ row_list = D.row_list;
     const double *__restrict__ kin = D.kin;
@@ -223,7 +228,6 @@ __global__ __launch_bounds__(kYzThreads) void k_yz_fwd(const cx<T> *__restrict__
     extern __shared__ __align__(16) unsigned char smem[];
     cx<T> *plane = reinterpret_cast<cx<T> *>(smem);
     cx<T> *tw = plane + N * N;
-    const int s = blockIdx.x;
     const int tid = threadIdx.x, nthr = blockDim.x;
     for (int i = tid; i < N; i += nthr) tw[i] = tw_g[i];
     cx<T> pre[MAXQ];
@@ -278,7 +282,8 @@ __global__ __launch_bounds__(256) void k_yz_inv_c(const cx<TIN> *__restrict__ ps
                                                   cx<T> *__restrict__ slab, int nslab, int bpw, int rows_max, int C) {
     KDesc D;
     int kk, b0, b1;
-    batch_block(kd, ba, bpw, D, kk, b0, b1);
+    int s;
+    batch_block(kd, ba, bpw, D, kk, b0, b1, s);
     const int *__restrict__ pt_off = D.pt_off, *__restrict__ pt_g = D.pt_g, *__restrict__ pt_pos = D.pt_pos;
     const int *__restrict__ row_off = D.row_off, *__restrict__ row_list = D.row_list;
     const cx<TIN> *psi = psi_all + ba.nb_total * (D.pw_off - ba.off0) + (int64_t)ba.b0 * D.npw;
@@ -289,7 +294,6 @@ __global__ __launch_bounds__(256) void k_yz_inv_c(const cx<TIN> *__restrict__ ps
     cx<T> *ybuf = rows + rows_max * N;
     cx<T> *tw = ybuf + N * C;
     int *map = reinterpret_cast<int *>(tw + N);
-    const int s = blockIdx.x;
     const int tid = threadIdx.x, nthr = blockDim.x;
     const int r0 = row_off[s], nr = row_off[s + 1] - r0;
     const int p0 = pt_off[s], p1 = pt_off[s + 1];
@@ -333,7 +337,8 @@ __global__ __launch_bounds__(256) void k_yz_fwd_c(const cx<T> *__restrict__ slab
                                                   int C) {
     KDesc D;
     int kk, b0, b1;
-    batch_block(kd, ba, bpw, D, kk, b0, b1);
+    int s;
+    batch_block(kd, ba, bpw, D, kk, b0, b1, s);
     const int *__restrict__ pt_off = D.pt_off, *__restrict__ pt_g = D.pt_g, *__restrict__ pt_pos = D.pt_pos;
     const int *__restrict__ row_off = D.row_off, *__restrict__ row_list = D.row_list;
     const double *__restrict__ kin = D.kin;
@@ -347,7 +352,6 @@ __global__ __launch_bounds__(256) void k_yz_fwd_c(const cx<T> *__restrict__ slab
     cx<T> *ybuf = rows + rows_max * N;
     cx<T> *tw = ybuf + N * C;
     int *map = reinterpret_cast<int *>(tw + N);
-    const int s = blockIdx.x;
     const int tid = threadIdx.x, nthr = blockDim.x;
     const int r0 = row_off[s], nr = row_off[s + 1] - r0;
     const int p0 = pt_off[s], p1 = pt_off[s + 1];
