@@ -205,10 +205,15 @@ int abacus_pw_profile_read(char *buf, int size);
  * yz_mode      y-z plane kernels: 0 automatic (whole plane in LDS when it fits), 1 whole
  *              plane, 2 compact (only the plane's z-column rows in LDS, y transforms in
  *              j3 chunks); planes that do not fit whole always use the compact form
+ * overlap      0 default (2), 1 the projector GEMMs run on a second stream of the library
+ *              (default priority) beside the local term: the projections from the start,
+ *              each band batch's B Q as soon as its local term is done; events order the
+ *              two streams and join the second back into the caller's stream before the
+ *              call returns, so stream semantics and graph capture are unchanged; 2 one stream
  * Results do not depend on the knobs beyond rounding (the split-K chunk changes the
  * summation grouping of the projections). Returns EBAD_SHAPE for invalid values.
  */
-int abacus_pw_set_tuning(int band_batch, int splitk_chunk, int yz_bands, int x_bands, int yz_mode);
+int abacus_pw_set_tuning(int band_batch, int splitk_chunk, int yz_bands, int x_bands, int yz_mode, int overlap);
 
 #ifdef __cplusplus
 }

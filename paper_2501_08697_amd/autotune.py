@@ -8,7 +8,8 @@ after one warm-up call. The winner is cached in a JSON file keyed by the
 problem's shape (grid, sphere sizes, projectors, bands, precision); the cache
 path is ABACUS_PW_AUTOTUNE_CACHE or ~/.cache/abacus_pw/autotune.json.
 
-The knobs change launch shapes and work-group band counts only; the split-K
+The knobs change launch shapes, work-group band counts and whether the
+projector GEMMs run on a second stream beside the local term; the split-K
 chunk changes the grouping of the projection sums, so results move at the
 rounding level (checked by the GPU tests).
 """
@@ -25,8 +26,9 @@ CANDIDATES = {
     "yz_bands": [1, 2, 4],
     "x_bands": [2, 4, 8],
     "splitk_chunk": [256, 512, 1024],
+    "overlap": [1, 2],
 }
-DEFAULT = {"band_batch": 0, "splitk_chunk": 0, "yz_bands": 0, "x_bands": 0, "yz_mode": 0}
+DEFAULT = {"band_batch": 0, "splitk_chunk": 0, "yz_bands": 0, "x_bands": 0, "yz_mode": 0, "overlap": 0}
 
 
 def cache_path() -> str:
@@ -39,7 +41,8 @@ def key(dp: B.DeviceProblem, nb: int, precision: int) -> str:
 
 
 def _apply(cfg):
-    B.set_tuning(cfg["band_batch"], cfg["splitk_chunk"], cfg["yz_bands"], cfg["x_bands"], cfg.get("yz_mode", 0))
+    B.set_tuning(cfg["band_batch"], cfg["splitk_chunk"], cfg["yz_bands"], cfg["x_bands"], cfg.get("yz_mode", 0),
+                 cfg.get("overlap", 0))
 
 
 def _time(dp, x, y, nb, precision, reps):

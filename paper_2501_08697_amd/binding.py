@@ -62,7 +62,7 @@ def lib():
         L.abacus_pw_fft_supported.argtypes = [i]
         L.abacus_pw_profile_enable.argtypes = [i]
         L.abacus_pw_profile_read.argtypes = [C.c_char_p, i]
-        L.abacus_pw_set_tuning.argtypes = [i, i, i, i, i]
+        L.abacus_pw_set_tuning.argtypes = [i, i, i, i, i, i]
         _lib = L
     return _lib
 
@@ -190,9 +190,11 @@ def plan_reset():
     check(lib().abacus_pw_plan_reset())
 
 
-def set_tuning(band_batch: int = 0, splitk_chunk: int = 0, yz_bands: int = 0, x_bands: int = 0, yz_mode: int = 0):
+def set_tuning(band_batch: int = 0, splitk_chunk: int = 0, yz_bands: int = 0, x_bands: int = 0, yz_mode: int = 0,
+               overlap: int = 0):
     """Process-wide kernel tuning knobs (0 = library default)."""
-    check(lib().abacus_pw_set_tuning(int(band_batch), int(splitk_chunk), int(yz_bands), int(x_bands), int(yz_mode)))
+    check(lib().abacus_pw_set_tuning(int(band_batch), int(splitk_chunk), int(yz_bands), int(x_bands), int(yz_mode),
+                                     int(overlap)))
 
 
 def profile_enable(on: bool = True):

@@ -114,10 +114,12 @@ int abacus_pw_plan_reset(void) {
     return guarded([&] { return plan_reset_all(); });
 }
 
-int abacus_pw_set_tuning(int band_batch, int splitk_chunk, int yz_bands, int x_bands, int yz_mode) {
-    if (band_batch < 0 || splitk_chunk < 0 || yz_bands < 0 || x_bands < 0 || yz_mode < 0 || yz_mode > 2)
-        return set_error(ABACUS_PW_EBAD_SHAPE, "tuning values must be >= 0 (yz_mode 0, 1 or 2)");
+int abacus_pw_set_tuning(int band_batch, int splitk_chunk, int yz_bands, int x_bands, int yz_mode, int overlap) {
+    if (band_batch < 0 || splitk_chunk < 0 || yz_bands < 0 || x_bands < 0 || yz_mode < 0 || yz_mode > 2 ||
+        overlap < 0 || overlap > 2)
+        return set_error(ABACUS_PW_EBAD_SHAPE, "tuning values must be >= 0 (yz_mode and overlap 0, 1 or 2)");
     g_yz_mode = yz_mode;
+    g_overlap = overlap;
     g_band_batch = band_batch;
     g_splitk_chunk = splitk_chunk;
     g_yz_bands = yz_bands;

@@ -1,9 +1,10 @@
-// H psi over every k-point: the local term on the grid (local.hip) followed
-// by the Kleinman-Bylander term as two MFMA GEMMs (gemm.hip):
+// H psi over every k-point: the local term on the grid (local.hip) and the
+// Kleinman-Bylander term as two MFMA GEMMs (gemm.hip):
 //   P = B^H psi  (nproj x nb per k),  Q = D P (atom blocks),  H psi += B Q.
 #include "hamiltonian.hpp"
 
 #include <algorithm>
+#include <mutex>
 
 #include "convert.hpp"
 #include "gemm.hpp"
@@ -40,10 +41,52 @@ int operator_copies(const abacus_pw_problem &p, Plan &P, bool need_v32, bool nee
     return ABACUS_PW_OK;
 }
 
-// H psi for nb bands of k-point k: psi, hpsi are that k's [nb][npw_k] blocks.
+namespace {
+
+// A second stream per device (default priority, non-blocking) on which the
+// projector GEMMs run beside the local term. Events fork it from the caller's
+// stream and join it back before the call returns.
+struct SideStream {
+    hipStream_t s = nullptr;
+    hipEvent_t fork = nullptr, step = nullptr, join = nullptr;
+};
+constexpr int kMaxDevices = 64;
+std::mutex g_side_mu;
+SideStream g_side[kMaxDevices];
+
+int side_stream(SideStream **out) {
+    int dev = 0;
+    APW_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) return set_error(ABACUS_PW_EINTERNAL, "device index out of range");
+    std::lock_guard<std::mutex> l(g_side_mu);
+    SideStream &ss = g_side[dev];
+    if (!ss.s) {
+        APW_HIP(hipStreamCreateWithFlags(&ss.s, hipStreamNonBlocking));
+        APW_HIP(hipEventCreateWithFlags(&ss.fork, hipEventDisableTiming));
+        APW_HIP(hipEventCreateWithFlags(&ss.step, hipEventDisableTiming));
+        APW_HIP(hipEventCreateWithFlags(&ss.join, hipEventDisableTiming));
+    }
+    *out = &ss;
+    return ABACUS_PW_OK;
+}
+
+// Work enqueued on `to` after this call runs after the work already on `from`.
+int order(hipEvent_t e, hipStream_t from, hipStream_t to) {
+    APW_HIP(hipEventRecord(e, from));
+    APW_HIP(hipStreamWaitEvent(to, e, 0));
+    return ABACUS_PW_OK;
+}
+
+}  // namespace
+
 // H psi for nb bands at the k-points [k0, k1): psi and hpsi start at k0's [nb][npw_k] block.
-// The local term runs every k-point of a band batch in one launch per pass; the
-// projector GEMMs run per k-point.
+// The local term runs every k-point of a band batch in one launch per pass and
+// writes hpsi = (T + V) psi; the projector GEMMs run per k-point: the
+// projections Q_k = D B_k^H psi_k, then hpsi += B_k Q_k. With the overlap knob on
+// the projections start on the side stream at once and each band batch's B Q
+// follows there as soon as that batch's local term is done, so the GEMMs share
+// the GPU with the plane passes. Off by default: on the 72^3 / 23847-PW case the
+// concurrent kernels slow each other down about as much as they overlap.
 int apply_h_range(const abacus_pw_problem &p, Plan &P, int k0, int k1, int prec, int nb, const void *psi, void *hpsi,
                   hipStream_t st, bool refresh_copies) {
     const bool bf = prec == ABACUS_PW_MIXED_BF16;
@@ -56,44 +99,75 @@ int apply_h_range(const abacus_pw_problem &p, Plan &P, int k0, int k1, int prec,
     APW_TRY(P.slab.ensure(local_slab_bytes(P, fft_prec, (k1 - k0) * bb)));
     if (refresh_copies) APW_TRY(operator_copies(p, P, fft_prec == 1, gemm_prec == 1 && !bf, st, bf));
     const void *v = fft_prec == 0 ? static_cast<const void *>(p.vloc) : P.vloc32.ptr;
-    APW_TRY(local_term(P, k0, k1, fft_prec, io_prec, v, psi, hpsi, nb, P.slab.ptr, bb, st));
-    if (P.nproj == 0) return ABACUS_PW_OK;
-    const size_t gb = gemm_prec == 0 ? 16 : 8;   // bytes per GEMM operand element
-    APW_TRY(P.projq.ensure((size_t)nb * P.nproj * gb));
+    if (P.nproj == 0) return local_term(P, k0, k1, fft_prec, io_prec, v, psi, hpsi, nb, P.slab.ptr, bb, st);
+
+    const size_t gb = gemm_prec == 0 ? 16 : 8;   // bytes per element of Q (complex64 in the BF16 mode)
+    const size_t qk = (size_t)nb * P.nproj * gb; // Q bytes per k-point
+    APW_TRY(P.projq.ensure(qk * (k1 - k0)));
     if (bf)
         APW_TRY(P.gemm_part.ensure(gemm_cn_bf16_part_bytes(P.nproj, nb, P.max_npw, g_splitk_chunk)));
     else
         APW_TRY(P.gemm_part.ensure(gemm_cn_part_bytes(P.nproj, nb, P.max_npw, (int)gb, g_splitk_chunk)));
     if (prec == ABACUS_PW_MIXED_FP32) APW_TRY(P.tmp_io.ensure((size_t)nb * P.max_npw * 8));
+
+    const bool overlap = g_overlap == 1;
+    SideStream *ss = nullptr;
+    hipStream_t gs = st;
+    if (overlap) {
+        APW_TRY(side_stream(&ss));
+        gs = ss->s;
+        APW_TRY(order(ss->fork, st, gs));
+    }
+    auto beta_k = [&](const KTables &K) -> const void * {
+        if (bf) return P.betabf.as<char>() + (size_t)P.nproj * K.pw_off * 4;
+        return gemm_prec == 0 ? static_cast<const void *>(static_cast<const char *>(p.beta) + (size_t)P.nproj * K.pw_off * 16)
+                              : static_cast<const void *>(P.beta32.as<char>() + (size_t)P.nproj * K.pw_off * 8);
+    };
+    // Q_k = D B_k^H psi_k
     for (int k = k0; k < k1; ++k) {
         const KTables &K = P.k[k];
-        const size_t eoff = (size_t)nb * (K.pw_off - P.pw_off[k0]);
-        const char *xk = static_cast<const char *>(psi) + eoff * ib;
-        char *yk = static_cast<char *>(hpsi) + eoff * ib;
+        const char *xk = static_cast<const char *>(psi) + (size_t)nb * (K.pw_off - P.pw_off[k0]) * ib;
+        void *qk_ptr = P.projq.as<char>() + qk * (k - k0);
+        const void *bk = beta_k(K);
         if (bf) {
-            const void *bk = P.betabf.as<char>() + (size_t)P.nproj * K.pw_off * 4;
             APW_TRY(proj_dapply_bf16(P.nproj, nb, K.npw, bk, K.npw, xk, 1, K.npw, p.dmat, P.proj_blk_lo, P.proj_blk_n,
-                                     P.proj_blk_doff, P.projq.ptr, P.gemm_part.ptr, g_splitk_chunk, st));
-            APW_TRY(gemm_nn_bf16_into_f64(nb, K.npw, P.nproj, P.projq.ptr, P.nproj, bk, K.npw, yk, K.npw, st));
+                                     P.proj_blk_doff, qk_ptr, P.gemm_part.ptr, g_splitk_chunk, gs));
             continue;
         }
-        const void *bk = gemm_prec == 0
-                             ? static_cast<const void *>(static_cast<const char *>(p.beta) + (size_t)P.nproj * K.pw_off * 16)
-                             : static_cast<const void *>(P.beta32.as<char>() + (size_t)P.nproj * K.pw_off * 8);
         const void *xg = xk;
         if (prec == ABACUS_PW_MIXED_FP32) {
             APW_TRY(convert_f64_to_f32(2 * (int64_t)nb * K.npw, reinterpret_cast<const double *>(xk),
-                                       P.tmp_io.as<float>(), st));
+                                       P.tmp_io.as<float>(), gs));
             xg = P.tmp_io.ptr;
         }
         APW_TRY(proj_dapply(gemm_prec, P.nproj, nb, K.npw, bk, K.npw, xg, K.npw, p.dmat, P.proj_blk_lo, P.proj_blk_n,
-                            P.proj_blk_doff, nullptr, P.projq.ptr, P.gemm_part.ptr, g_splitk_chunk, st));
-        if (prec == ABACUS_PW_MIXED_FP32)
-            APW_TRY(gemm_nn_f32_into_f64(nb, K.npw, P.nproj, P.projq.ptr, P.nproj, bk, K.npw, yk, K.npw, 1.0, 1.0, st));
-        else
-            APW_TRY(gemm_nn(gemm_prec, nb, K.npw, P.nproj, P.projq.ptr, P.nproj, bk, K.npw, yk, K.npw, 1.0, 1.0, st));
+                            P.proj_blk_doff, nullptr, qk_ptr, P.gemm_part.ptr, g_splitk_chunk, gs));
     }
-    return ABACUS_PW_OK;
+    // hpsi[b0 .. b0+bbt) += B_k Q_k[b0 .. b0+bbt) for every k-point
+    auto add_bq = [&](int b0, int bbt, hipStream_t s) -> int {
+        for (int k = k0; k < k1; ++k) {
+            const KTables &K = P.k[k];
+            char *yk = static_cast<char *>(hpsi) + ((size_t)nb * (K.pw_off - P.pw_off[k0]) + (size_t)b0 * K.npw) * ib;
+            const char *qb = P.projq.as<char>() + qk * (k - k0) + (size_t)b0 * P.nproj * gb;
+            const void *bk = beta_k(K);
+            if (bf)
+                APW_TRY(gemm_nn_bf16_into_f64(bbt, K.npw, P.nproj, qb, P.nproj, bk, K.npw, yk, K.npw, s));
+            else if (prec == ABACUS_PW_MIXED_FP32)
+                APW_TRY(gemm_nn_f32_into_f64(bbt, K.npw, P.nproj, qb, P.nproj, bk, K.npw, yk, K.npw, 1.0, 1.0, s));
+            else
+                APW_TRY(gemm_nn(gemm_prec, bbt, K.npw, P.nproj, qb, P.nproj, bk, K.npw, yk, K.npw, 1.0, 1.0, s));
+        }
+        return ABACUS_PW_OK;
+    };
+    if (!overlap) {
+        APW_TRY(local_term(P, k0, k1, fft_prec, io_prec, v, psi, hpsi, nb, P.slab.ptr, bb, st));
+        return add_bq(0, nb, st);
+    }
+    APW_TRY(local_term(P, k0, k1, fft_prec, io_prec, v, psi, hpsi, nb, P.slab.ptr, bb, st, [&](int b0, int bbt) -> int {
+        APW_TRY(order(ss->step, st, gs));
+        return add_bq(b0, bbt, gs);
+    }));
+    return order(ss->join, gs, st);
 }
 
 int apply_h_k(const abacus_pw_problem &p, Plan &P, int k, int prec, int nb, const void *psi, void *hpsi,

@@ -676,7 +676,8 @@ int local_gradv_finish(const Plan &P, const double *part, int G, double *grad_v,
 }
 
 int local_term(const Plan &P, int k0, int k1, int fft_prec, int io_prec, const void *vloc, const void *psi,
-               void *hpsi, int nb, void *slab, int band_batch, hipStream_t st) {
+               void *hpsi, int nb, void *slab, int band_batch, hipStream_t st,
+               const std::function<int(int, int)> &after_batch) {
     const int nkb = k1 - k0;
     for (int b0 = 0; b0 < nb; b0 += band_batch) {
         const BatchArgs ba{nb, P.pw_off[k0], b0, std::min(band_batch, nb - b0)};
@@ -694,6 +695,7 @@ int local_term(const Plan &P, int k0, int k1, int fft_prec, int io_prec, const v
             APW_TRY((dispatch_x<float>(P, vloc, slab, nv, st)));
             APW_TRY((dispatch_yz<float, double>(false, P, k0, nkb, ba, psi, hpsi, slab, st)));
         }
+        if (after_batch) APW_TRY(after_batch(b0, ba.bbt));
     }
     return ABACUS_PW_OK;
 }

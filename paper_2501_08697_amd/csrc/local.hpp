@@ -1,6 +1,8 @@
 // Local-potential term of H psi (grid transforms); see local.hip.
 #pragma once
 
+#include <functional>
+
 #include "plan.hpp"
 
 namespace apw {
@@ -16,8 +18,11 @@ size_t local_slab_bytes(const Plan &P, int fft_prec, int nbands);
 // k0's [nb][npw_k] block, k blocks back to back. Each band batch runs every k-point in one
 // launch per pass. fft_prec: 0 FP64, 1 FP32 transforms. io_prec: 0 complex128, 1 complex64.
 // vloc: float64 grid for fft_prec 0, float32 for 1. slab: local_slab_bytes((k1-k0) band_batch).
+// after_batch(b0, bbt), if given, is called once the kernels of bands [b0, b0+bbt)
+// are enqueued (their H psi rows are complete when that work has run on st).
 int local_term(const Plan &P, int k0, int k1, int fft_prec, int io_prec, const void *vloc, const void *psi,
-               void *hpsi, int nb, void *slab, int band_batch, hipStream_t st);
+               void *hpsi, int nb, void *slab, int band_batch, hipStream_t st,
+               const std::function<int(int, int)> &after_batch = nullptr);
 
 // Inverse y-z transforms of bands [b0, b0+bbt) at the k-points [k0, k1) into slab planes
 // (virtual band (k - k0) * bbt + b); psi starts at k0's block of nb bands.

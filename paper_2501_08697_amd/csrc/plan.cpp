@@ -22,6 +22,7 @@ int g_splitk_chunk = 0;
 int g_yz_bands = 0;
 int g_x_bands = 0;
 int g_yz_mode = 0;
+int g_overlap = 0;
 
 DeviceBuffer::~DeviceBuffer() {
     if (ptr) (void)hipFree(ptr);

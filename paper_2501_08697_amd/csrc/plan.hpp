@@ -107,6 +107,7 @@ extern int g_splitk_chunk;  // K chunk of the split-K projection GEMM
 extern int g_yz_bands;      // bands per y-z plane work-group
 extern int g_x_bands;       // bands per x-pass work-group
 extern int g_yz_mode;       // plane kernels: 0 auto, 1 full plane in LDS, 2 compact rows
+extern int g_overlap;       // projector GEMMs beside the local term: 0 default (off), 1 on, 2 off
 
 // Looks up or builds the plan for a problem (validates it on build).
 int get_plan(const abacus_pw_problem *p, Plan **out);

@@ -120,7 +120,8 @@ def test_error_message_is_set(prob):
 
 
 def test_tuning_rejects_negative():
-    assert code_name(B.lib().abacus_pw_set_tuning(-1, 0, 0, 0, 0)) == "EBAD_SHAPE"
-    assert code_name(B.lib().abacus_pw_set_tuning(0, 0, 0, -2, 0)) == "EBAD_SHAPE"
-    assert code_name(B.lib().abacus_pw_set_tuning(0, 0, 0, 0, 3)) == "EBAD_SHAPE"
-    assert B.lib().abacus_pw_set_tuning(0, 0, 0, 0, 0) == 0
+    assert code_name(B.lib().abacus_pw_set_tuning(-1, 0, 0, 0, 0, 0)) == "EBAD_SHAPE"
+    assert code_name(B.lib().abacus_pw_set_tuning(0, 0, 0, -2, 0, 0)) == "EBAD_SHAPE"
+    assert code_name(B.lib().abacus_pw_set_tuning(0, 0, 0, 0, 3, 0)) == "EBAD_SHAPE"
+    assert code_name(B.lib().abacus_pw_set_tuning(0, 0, 0, 0, 0, 3)) == "EBAD_SHAPE"
+    assert B.lib().abacus_pw_set_tuning(0, 0, 0, 0, 0, 0) == 0

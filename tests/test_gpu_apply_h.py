@@ -173,12 +173,12 @@ def test_large_plane_fp64_uses_compact_rows():
     assert rel(y32, oracle.apply_h(p, p.psi)) < 1e-5
 
 
-@pytest.mark.parametrize("mode", [1, 2])
-def test_plane_modes_and_tuning_agree(c2, c2_ref, mode):
-    """Whole-plane and compact-row kernels, odd band groups and a small batch: same H psi."""
+@pytest.mark.parametrize("mode,overlap", [(1, 2), (2, 1)])
+def test_plane_modes_and_tuning_agree(c2, c2_ref, mode, overlap):
+    """Whole-plane and compact-row kernels, odd band groups, a small batch, one or two streams: same H psi."""
     b = B()
     try:
-        b.set_tuning(band_batch=24, splitk_chunk=512, yz_bands=3, x_bands=5, yz_mode=mode)
+        b.set_tuning(band_batch=24, splitk_chunk=512, yz_bands=3, x_bands=5, yz_mode=mode, overlap=overlap)
         y = gpu_apply(c2)
         assert rel(y, c2_ref) < 1e-12
         y32 = gpu_apply(c2, prec=b.FP32)
@@ -196,3 +196,26 @@ def test_c3_c4_geometry_fp64(cfg):
     p = W.make_problem(W.tiny_config(**cfg))
     y = gpu_apply(p)
     assert rel(y, oracle.apply_h(p, p.psi)) < 1e-12
+
+
+@pytest.mark.parametrize("prec", [0, 1, 2, 3])
+def test_overlap_is_bitwise_one_stream(prec):
+    """Projector GEMMs on the side stream (per band batch, several uneven k-points) == one stream, bit for bit."""
+    b = B()
+    p = W.make_problem(W.tiny_config(fft=24, ecut=24.0, a=8.0, nb=40, natom=4,
+                                     kfrac=((0.0, 0.0, 0.0), (0.5, 0.0, 0.0), (0.5, 0.5, 0.5))))
+    print(f"[overlap] npw={list(p.npw)} nb={p.nb} prec={prec}", flush=True)
+    dp = b.DeviceProblem(p)
+    x = torch.from_numpy(p.psi).cuda()
+    if prec == b.FP32:
+        x = x.to(torch.complex64)
+    out = {}
+    try:
+        for ov in (1, 2):
+            b.set_tuning(band_batch=16, overlap=ov)
+            out[ov] = b.apply_h(dp, x, prec).cpu().numpy()
+    finally:
+        b.set_tuning()
+    assert np.array_equal(out[1], out[2])
+    tol = {0: 1e-12, 1: 1e-5, 2: 2e-2, 3: 1e-5}[prec]
+    assert rel(out[1], oracle.apply_h(p, p.psi)) < tol
