@@ -121,8 +121,8 @@ __global__ __launch_bounds__(kYzThreads) void k_yz_inv(const cx<TIN> *__restrict
 //   O  task (c, ka): slots B ka + jb from LDS; forward DFT_B; the slots that
 //      belong to the slab go straight to HBM.
 // So each element crosses LDS twice per band (once per transpose) and there
-// are three barriers per band. The next band's phase-I values are fetched
-// while the current band finishes. The tile width keeps w3 B <= 256, so every
+// are three barriers per band. The next band's phase-I values are fetched as
+// soon as phase I has consumed the current ones, behind phases F and O. The tile width keeps w3 B <= 256, so every
 // thread owns at most one task per phase.
 template <int N1, typename T, typename TV>
 __global__ __launch_bounds__(256) void k_xpass(cx<T> *__restrict__ slab, int nslab, int N2, int N3, int T3, int nt3,
@@ -168,6 +168,12 @@ __global__ __launch_bounds__(256) void k_xpass(cx<T> *__restrict__ slab, int nsl
             cx<T> z[B];
 #pragma unroll
             for (int kb = 0; kb < B; ++kb) z[kb] = pre[kb];
+            // the next band's values are fetched now, behind phases F and O
+            if (b + 1 < b1) {
+#pragma unroll
+                for (int kb = 0; kb < B; ++kb)
+                    if (src[kb] >= 0) pre[kb] = base[(b + 1) * bstride + src[kb]];
+            }
             RegDft<B, +1, T>::run(z);
             tile[(B * ka) * T3 + c] = z[0];
 #pragma unroll
@@ -187,11 +193,6 @@ __global__ __launch_bounds__(256) void k_xpass(cx<T> *__restrict__ slab, int nsl
             for (int q = 1; q < A; ++q) tile[(jb + B * q) * T3 + c] = cmulc(a[q], tw[jb * A + q]);
         }
         __syncthreads();
-        if (b + 1 < b1) {
-#pragma unroll
-            for (int kb = 0; kb < B; ++kb)
-                if (has_ka && src[kb] >= 0) pre[kb] = base[(b + 1) * bstride + src[kb]];
-        }
         if (has_ka) {
             cx<T> z[B];
 #pragma unroll
@@ -206,7 +207,9 @@ __global__ __launch_bounds__(256) void k_xpass(cx<T> *__restrict__ slab, int nsl
 }
 
 // One work-group per (plane s, group of bands); the next band's plane is
-// fetched into registers while the current one transforms.
+// fetched into registers while the current one transforms, and so is this
+// band's psi at the plane's sphere points (whose indices and |k+G|^2 are read
+// once for all bands).
 template <int N, typename T, typename TIO>
 __global__ __launch_bounds__(kYzThreads) void k_yz_fwd(const cx<T> *__restrict__ slab, int nslab,
                                                        const KDesc *__restrict__ kd, BatchArgs ba,
@@ -242,6 +245,19 @@ __global__ __launch_bounds__(kYzThreads) void k_yz_fwd(const cx<T> *__restrict__
     const int r0 = row_off[s], nr = row_off[s + 1] - r0;
     const int p0 = pt_off[s], p1 = pt_off[s + 1];
     const TIO sc = static_cast<TIO>(inv_n);
+    // the plane's first MAXP * nthr sphere points: index, LDS slot and |k+G|^2
+    // held in registers for every band (clamped to point 0 where a slot is unused)
+    constexpr int MAXP = 4;
+    int gi[MAXP], lp[MAXP];
+    TIO kq[MAXP];
+#pragma unroll
+    for (int q = 0; q < MAXP; ++q) {
+        const int p = min(p0 + tid + q * nthr, p1 - 1);
+        gi[q] = p >= p0 ? pt_g[p] : 0;
+        lp[q] = p >= p0 ? pt_pos[p] : 0;
+    }
+#pragma unroll
+    for (int q = 0; q < MAXP; ++q) kq[q] = static_cast<TIO>(kin[gi[q]]);
     for (int b = b0; b < b1; ++b) {
 #pragma unroll
         for (int q = 0; q < MAXQ; ++q) {
@@ -249,6 +265,11 @@ __global__ __launch_bounds__(kYzThreads) void k_yz_fwd(const cx<T> *__restrict__
             if (i < N * N) plane[i] = pre[q];
         }
         __syncthreads();
+        const cx<TIO> *x = psi + b * ld;
+        cx<TIO> *y = hpsi + b * ld;
+        cx<TIO> xq[MAXP];   // this band's psi at the thread's points, fetched behind the transforms
+#pragma unroll
+        for (int q = 0; q < MAXP; ++q) xq[q] = x[gi[q]];
         if (b + 1 < b1) {
             const cx<T> *in = slab + ((int64_t)(b + 1) * nslab + s) * (int64_t)(N * N);
 #pragma unroll
@@ -259,9 +280,13 @@ __global__ __launch_bounds__(kYzThreads) void k_yz_fwd(const cx<T> *__restrict__
         }
         lds_fft<N, -1, true>(plane, N, [](int l) { return l; }, N, tw);
         lds_fft<N, -1, false>(plane, nr, [=](int l) { return row_list[r0 + l] * N; }, 1, tw);
-        const cx<TIO> *x = psi + b * ld;
-        cx<TIO> *y = hpsi + b * ld;
-        for (int p = p0 + tid; p < p1; p += nthr) {
+#pragma unroll
+        for (int q = 0; q < MAXP; ++q)
+            if (p0 + tid + q * nthr < p1) {
+                const cx<TIO> v = cvt<TIO>(plane[lp[q]]);
+                y[gi[q]] = cx<TIO>{kq[q] * xq[q].re + sc * v.re, kq[q] * xq[q].im + sc * v.im};
+            }
+        for (int p = p0 + MAXP * nthr + tid; p < p1; p += nthr) {
             const int g = pt_g[p];
             const cx<TIO> v = cvt<TIO>(plane[pt_pos[p]]);
             const TIO kg = static_cast<TIO>(kin[g]);
