@@ -101,17 +101,22 @@ KERNEL_SOURCES = {
 }
 
 
-def measured_traffic(kernel):
-    """HBM bytes per launch from the committed counter summary, if it matches the current source."""
+def measured_traffic(kernel, bands_per_launch):
+    """HBM bytes per launch from the committed counter summary, if it matches the current source.
+
+    The summary was taken at its own launch shape (`bands_per_launch:` in the file);
+    the bytes scale with the bands one launch processes, so they are rescaled to
+    the launch shape timed here."""
     path = os.path.join(ROOT, "profiles", f"traffic_{kernel}_{WORKLOAD}.txt")
     if not os.path.exists(path):
         return None
     txt = open(path).read()
     m = re.search(r"source_hash:\s*(\w+)", txt)
     b = re.search(r"hbm_bytes_per_launch:\s*([0-9.eE+]+)", txt)
-    if not m or not b or m.group(1) != source_hash(KERNEL_SOURCES[kernel]):
+    nb = re.search(r"bands_per_launch:\s*([0-9]+)", txt)
+    if not m or not b or not nb or m.group(1) != source_hash(KERNEL_SOURCES[kernel]):
         return None
-    return float(b.group(1))
+    return float(b.group(1)) * bands_per_launch / int(nb.group(1))
 
 
 def cpu_baseline(prob):
@@ -223,7 +228,7 @@ def main():
         roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": achieved / HBM_PEAK_GBS}
     roof["kernel"] = dom
-    roof["traffic"] = measured_traffic(dom)
+    roof["traffic"] = measured_traffic(dom, nb / d["launches_per_step"])
     for r in rows.values():
         if r["alg_flops"]:
             r["tflops"] = r["alg_flops"] / (r["avg_ms"] * 1e-3) / 1e12
