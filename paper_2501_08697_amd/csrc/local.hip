@@ -55,6 +55,20 @@ constexpr int kXBands = 4;     // bands per x-pass work-group
 constexpr int kYzThreads = 512; // threads of a y-z plane work-group
 constexpr int kYzBandsDefault = 2; // bands per y-z plane work-group
 
+// Copy an N x N plane from LDS to global memory, kYzThreads threads, four
+// elements per thread in flight (LDS reads first, then the stores).
+template <int N, typename T> __device__ __forceinline__ void store_plane(const cx<T> *plane, cx<T> *out, int tid) {
+    constexpr int NN = N * N, U = 4;
+    for (int i0 = tid; i0 < NN; i0 += U * kYzThreads) {
+        cx<T> v[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) v[u] = plane[min(i0 + u * kYzThreads, NN - 1)];
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            if (i0 + u * kYzThreads < NN) out[i0 + u * kYzThreads] = v[u];
+    }
+}
+
 // One work-group per (plane s, group of bands). The plane's point list is read
 // once into registers; while band b transforms, the sphere values of band b+1
 // are already being fetched.
@@ -75,19 +89,26 @@ __global__ __launch_bounds__(kYzThreads) void k_yz_inv(const cx<TIN> *__restrict
     extern __shared__ __align__(16) unsigned char smem[];
     cx<T> *plane = reinterpret_cast<cx<T> *>(smem);
     cx<T> *tw = plane + N * N;
+    int *rows = reinterpret_cast<int *>(tw + N);   // the plane's z-column rows (times N), read once
     const int tid = threadIdx.x, nthr = blockDim.x;
     for (int i = tid; i < N; i += nthr) tw[i] = tw_g[i];
+    const int r0 = row_off[s], nr = row_off[s + 1] - r0;
+    for (int i = tid; i < nr; i += nthr) rows[i] = row_list[r0 + i] * N;
     const int p0 = pt_off[s], p1 = pt_off[s + 1];
-    int gi[MAXP], lp[MAXP];
+    // gi = -1 marks an unused slot; gc is a valid index for every slot, so the
+    // loads are issued unconditionally (one wait for all of them, not one each)
+    int gi[MAXP], gc[MAXP], lp[MAXP];
     cx<TIN> pre[MAXP];
 #pragma unroll
     for (int q = 0; q < MAXP; ++q) {
         const int p = p0 + tid + q * nthr;
-        gi[q] = p < p1 ? pt_g[p] : -1;
-        lp[q] = p < p1 ? pt_pos[p] : 0;
-        pre[q] = gi[q] >= 0 ? psi[b0 * ldpsi + gi[q]] : cx<TIN>{TIN(0), TIN(0)};
+        const int pc = p1 > p0 ? min(p, p1 - 1) : 0;
+        gc[q] = pt_g[pc];
+        gi[q] = p < p1 ? gc[q] : -1;
+        lp[q] = pt_pos[pc];
     }
-    const int r0 = row_off[s], nr = row_off[s + 1] - r0;
+#pragma unroll
+    for (int q = 0; q < MAXP; ++q) pre[q] = psi[b0 * ldpsi + gc[q]];
     for (int b = b0; b < b1; ++b) {
         for (int i = tid; i < N * N; i += nthr) plane[i] = czero<T>();
         __syncthreads();
@@ -98,13 +119,12 @@ __global__ __launch_bounds__(kYzThreads) void k_yz_inv(const cx<TIN> *__restrict
         __syncthreads();
         if (b + 1 < b1) {
 #pragma unroll
-            for (int q = 0; q < MAXP; ++q)
-                if (gi[q] >= 0) pre[q] = psi[(b + 1) * ldpsi + gi[q]];
+            for (int q = 0; q < MAXP; ++q) pre[q] = psi[(b + 1) * ldpsi + gc[q]];
         }
-        lds_fft<N, +1, false>(plane, nr, [=](int l) { return row_list[r0 + l] * N; }, 1, tw);
+        lds_fft<N, +1, false>(plane, nr, [=](int l) { return rows[l]; }, 1, tw);
         lds_fft<N, +1, true>(plane, N, [](int l) { return l; }, N, tw);
         cx<T> *out = slab + ((int64_t)b * nslab + s) * (int64_t)(N * N);
-        for (int i = tid; i < N * N; i += nthr) out[i] = plane[i];
+        store_plane<N>(plane, out, tid);
         __syncthreads();
     }
 }
@@ -231,8 +251,11 @@ __global__ __launch_bounds__(kYzThreads) void k_yz_fwd(const cx<T> *__restrict__
     extern __shared__ __align__(16) unsigned char smem[];
     cx<T> *plane = reinterpret_cast<cx<T> *>(smem);
     cx<T> *tw = plane + N * N;
+    int *rows = reinterpret_cast<int *>(tw + N);   // the plane's z-column rows (times N), read once
     const int tid = threadIdx.x, nthr = blockDim.x;
     for (int i = tid; i < N; i += nthr) tw[i] = tw_g[i];
+    const int r0 = row_off[s], nr = row_off[s + 1] - r0;
+    for (int i = tid; i < nr; i += nthr) rows[i] = row_list[r0 + i] * N;
     cx<T> pre[MAXQ];
     {
         const cx<T> *in = slab + ((int64_t)b0 * nslab + s) * (int64_t)(N * N);
@@ -242,7 +265,6 @@ __global__ __launch_bounds__(kYzThreads) void k_yz_fwd(const cx<T> *__restrict__
             pre[q] = i < N * N ? in[i] : czero<T>();
         }
     }
-    const int r0 = row_off[s], nr = row_off[s + 1] - r0;
     const int p0 = pt_off[s], p1 = pt_off[s + 1];
     const TIO sc = static_cast<TIO>(inv_n);
     // the plane's first MAXP * nthr sphere points: index, LDS slot and |k+G|^2
@@ -279,7 +301,7 @@ __global__ __launch_bounds__(kYzThreads) void k_yz_fwd(const cx<T> *__restrict__
             }
         }
         lds_fft<N, -1, true>(plane, N, [](int l) { return l; }, N, tw);
-        lds_fft<N, -1, false>(plane, nr, [=](int l) { return row_list[r0 + l] * N; }, 1, tw);
+        lds_fft<N, -1, false>(plane, nr, [=](int l) { return rows[l]; }, 1, tw);
 #pragma unroll
         for (int q = 0; q < MAXP; ++q)
             if (p0 + tid + q * nthr < p1) {
@@ -511,7 +533,7 @@ template <int N, typename T> static int compact_chunk(int rows_max) {
 template <int N, typename T, typename TIO>
 static int launch_yz(bool inverse, const Plan &P, int k0, int nkb, const BatchArgs &ba, const void *psi,
                      void *hpsi, void *slab, hipStream_t st) {
-    const size_t lds_full = (size_t)(N * N + N) * sizeof(cx<T>);
+    const size_t lds_full = (size_t)(N * N + N) * sizeof(cx<T>) + (size_t)N * sizeof(int);   // plane, twiddles, rows
     const int Cc = compact_chunk<N, T>(P.max_rows);
     const bool full_fits = lds_full <= kLdsLimit;
     const bool compact = g_yz_mode == 2 || !full_fits;
