@@ -9,9 +9,10 @@
 //       (combinations of basis vectors: Y += B Q, Psi = V Y)
 //
 // Tiles: a 256-thread work-group owns a 64 x 64 output tile; each of its four
-// waves a 32 x 32 quarter as 2 x 2 blocks of 16 x 16 MFMA results, one block
-// for the real and one for the imaginary part. Operands are staged in LDS
-// (16 k per stage). FP64 uses v_mfma_f64_16x16x4f64, FP32 v_mfma_f32_16x16x4f32;
+// waves a 32 x 32 quarter as 2 x 2 blocks of 16 x 16 MFMA results. A complex
+// product takes three real products (3M: ar br, ai bi and the product of the
+// sums, from which the real and imaginary parts follow), so each block keeps
+// three accumulators. Operands are staged in LDS (16 k per stage). FP64 uses v_mfma_f64_16x16x4f64, FP32 v_mfma_f32_16x16x4f32;
 // both take one value of A and of B per lane (A[i][k] at lane i + 16 k, B[k][j]
 // at lane j + 16 k) and return four values per lane in column j = lane % 16.
 // The row of element e differs: the FP64 instruction interleaves rows
@@ -40,11 +41,15 @@ template <> struct Acc<float> {
 };
 
 constexpr int TM = 64, TN = 64, KT = 16, KP = KT + 1;
+// Asking for at least two waves per SIMD makes the compiler keep the twelve
+// accumulator blocks in ordinary VGPRs (166 in FP64, three waves per SIMD)
+// instead of spreading them over VGPRs and AGPRs (278, one wave per SIMD).
+constexpr int kGemmWaves = 2;
 
 // ----------------------------------------------------------------- CN ------
 // part[s][j][i] = sum over k in split s of conj(A[i][k]) B[j][k]
 template <typename T>
-__global__ __launch_bounds__(256) void k_gemm_cn_part(int M, int N, int K, int kchunk, const cx<T> *__restrict__ A,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kGemmWaves))) void k_gemm_cn_part(int M, int N, int K, int kchunk, const cx<T> *__restrict__ A,
                                                       int64_t lda, const cx<T> *__restrict__ B, int64_t ldb,
                                                       cx<T> *__restrict__ part) {
     __shared__ cx<T> As[TM][KP];
@@ -55,11 +60,11 @@ __global__ __launch_bounds__(256) void k_gemm_cn_part(int M, int N, int K, int k
     const int i0 = bx * TM, j0 = by * TN, s = bz;
     const int kb = s * kchunk, ke = min(K, kb + kchunk);
     using AV = typename Acc<T>::V;
-    AV cre[2][2], cim[2][2];
+    AV c1[2][2], c2[2][2], c3[2][2];   // sums of ar br, ai bi, (ar - ai)(br + bi)
 #pragma unroll
     for (int a = 0; a < 2; ++a)
 #pragma unroll
-        for (int b = 0; b < 2; ++b) cre[a][b] = cim[a][b] = Acc<T>::zero();
+        for (int b = 0; b < 2; ++b) c1[a][b] = c2[a][b] = c3[a][b] = Acc<T>::zero();
     const int lr = tid >> 2, lk = (tid & 3) * 4;   // loader: row, first k of 4
     const int wi = (w & 1) * 32, wj = (w >> 1) * 32;
     const int gi = i0 + lr, gj = j0 + lr;
@@ -89,15 +94,20 @@ __global__ __launch_bounds__(256) void k_gemm_cn_part(int M, int N, int K, int k
             for (int r = 0; r < 2; ++r) a[r] = As[wi + 16 * r + (lane & 15)][kk];
 #pragma unroll
             for (int c = 0; c < 2; ++c) b[c] = Bs[wj + 16 * c + (lane & 15)][kk];
+            T as[2], bs[2];
+#pragma unroll
+            for (int r = 0; r < 2; ++r) as[r] = a[r].re - a[r].im;
+#pragma unroll
+            for (int c = 0; c < 2; ++c) bs[c] = b[c].re + b[c].im;
 #pragma unroll
             for (int r = 0; r < 2; ++r)
 #pragma unroll
                 for (int c = 0; c < 2; ++c) {
-                    // conj(a) b = (ar br + ai bi) + i (ar bi - ai br)
-                    cre[r][c] = Acc<T>::mma(a[r].re, b[c].re, cre[r][c]);
-                    cre[r][c] = Acc<T>::mma(a[r].im, b[c].im, cre[r][c]);
-                    cim[r][c] = Acc<T>::mma(a[r].re, b[c].im, cim[r][c]);
-                    cim[r][c] = Acc<T>::mma(-a[r].im, b[c].re, cim[r][c]);
+                    // conj(a) b with three real products:
+                    //   re = ar br + ai bi,  im = (ar - ai)(br + bi) - ar br + ai bi
+                    c1[r][c] = Acc<T>::mma(a[r].re, b[c].re, c1[r][c]);
+                    c2[r][c] = Acc<T>::mma(a[r].im, b[c].im, c2[r][c]);
+                    c3[r][c] = Acc<T>::mma(as[r], bs[c], c3[r][c]);
                 }
         }
         __syncthreads();
@@ -111,7 +121,8 @@ __global__ __launch_bounds__(256) void k_gemm_cn_part(int M, int N, int K, int k
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
                 const int gi = i0 + wi + 16 * r + Acc<T>::row(lane, e);
-                if (gi < M && gj < N) out[(int64_t)gj * M + gi] = cx<T>{cre[r][c][e], cim[r][c][e]};
+                if (gi < M && gj < N)
+                    out[(int64_t)gj * M + gi] = cx<T>{c1[r][c][e] + c2[r][c][e], c3[r][c][e] - c1[r][c][e] + c2[r][c][e]};
             }
         }
 }
@@ -176,7 +187,7 @@ __global__ __launch_bounds__(256) void k_reduce_dapply(int M, int nsplit, const 
 // ----------------------------------------------------------------- NN ------
 // C[j][g] = alpha * sum_i A[j][i] B[i][g] + beta * C[j][g]
 template <typename T, typename TC>
-__global__ __launch_bounds__(256) void k_gemm_nn(int M, int G, int K, const cx<T> *__restrict__ A, int64_t lda,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kGemmWaves))) void k_gemm_nn(int M, int G, int K, const cx<T> *__restrict__ A, int64_t lda,
                                                  const cx<T> *__restrict__ B, int64_t ldb, cx<TC> *__restrict__ C,
                                                  int64_t ldc, double alpha, double beta) {
     __shared__ cx<T> As[TM][KP];
@@ -186,11 +197,11 @@ __global__ __launch_bounds__(256) void k_gemm_nn(int M, int G, int K, const cx<T
     xcd_block(bx, by, bz);   // the row tiles of one column block share an L2
     const int j0 = bx * TM, g0 = by * TN;
     using AV = typename Acc<T>::V;
-    AV cre[2][2], cim[2][2];
+    AV c1[2][2], c2[2][2], c3[2][2];   // sums of ar br, ai bi, (ar + ai)(br + bi)
 #pragma unroll
     for (int a = 0; a < 2; ++a)
 #pragma unroll
-        for (int b = 0; b < 2; ++b) cre[a][b] = cim[a][b] = Acc<T>::zero();
+        for (int b = 0; b < 2; ++b) c1[a][b] = c2[a][b] = c3[a][b] = Acc<T>::zero();
     const int wj = (w & 1) * 32, wg = (w >> 1) * 32;
     const int ar = tid >> 2, ak = (tid & 3) * 4;       // A loader: row j, 4 consecutive i
     const int bk = tid >> 4, bg = (tid & 15) * 4;      // B loader: row i, 4 consecutive g
@@ -226,15 +237,20 @@ __global__ __launch_bounds__(256) void k_gemm_nn(int M, int G, int K, const cx<T
             for (int r = 0; r < 2; ++r) a[r] = As[wj + 16 * r + (lane & 15)][kk];
 #pragma unroll
             for (int c = 0; c < 2; ++c) b[c] = Bs[kk][wg + 16 * c + (lane & 15)];
+            T as[2], bs[2];
+#pragma unroll
+            for (int r = 0; r < 2; ++r) as[r] = a[r].re + a[r].im;
+#pragma unroll
+            for (int c = 0; c < 2; ++c) bs[c] = b[c].re + b[c].im;
 #pragma unroll
             for (int r = 0; r < 2; ++r)
 #pragma unroll
                 for (int c = 0; c < 2; ++c) {
-                    // a b = (ar br - ai bi) + i (ar bi + ai br)
-                    cre[r][c] = Acc<T>::mma(a[r].re, b[c].re, cre[r][c]);
-                    cre[r][c] = Acc<T>::mma(-a[r].im, b[c].im, cre[r][c]);
-                    cim[r][c] = Acc<T>::mma(a[r].re, b[c].im, cim[r][c]);
-                    cim[r][c] = Acc<T>::mma(a[r].im, b[c].re, cim[r][c]);
+                    // a b with three real products:
+                    //   re = ar br - ai bi,  im = (ar + ai)(br + bi) - ar br - ai bi
+                    c1[r][c] = Acc<T>::mma(a[r].re, b[c].re, c1[r][c]);
+                    c2[r][c] = Acc<T>::mma(a[r].im, b[c].im, c2[r][c]);
+                    c3[r][c] = Acc<T>::mma(as[r], bs[c], c3[r][c]);
                 }
         }
         __syncthreads();
@@ -249,7 +265,8 @@ __global__ __launch_bounds__(256) void k_gemm_nn(int M, int G, int K, const cx<T
                 const int gj = j0 + wj + 16 * r + Acc<T>::row(lane, e);
                 if (gj < M && gg < G) {
                     cx<TC> *p = C + (int64_t)gj * ldc + gg;
-                    double re = alpha * (double)cre[r][c][e], im = alpha * (double)cim[r][c][e];
+                    const double p1 = c1[r][c][e], p2 = c2[r][c][e], p3 = c3[r][c][e];
+                    double re = alpha * (p1 - p2), im = alpha * (p3 - p1 - p2);
                     if (beta != 0.0) {
                         const cx<TC> o = *p;
                         re += beta * (double)o.re;
