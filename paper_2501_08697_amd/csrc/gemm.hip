@@ -18,6 +18,8 @@
 // The row of element e differs: the FP64 instruction interleaves rows
 // (i = lane / 16 + 4 e), the FP32 one blocks them (i = 4 (lane / 16) + e);
 // Acc<T>::row encodes this (measured on gfx950).
+#include <algorithm>
+
 #include "common.hpp"
 #include "gemm.hpp"
 
@@ -134,12 +136,25 @@ __global__ void k_reduce(int M, int N, int nsplit, const cx<T> *__restrict__ par
     const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (idx >= (int64_t)M * N) return;
     const int j = (int)(idx / M), i = (int)(idx - (int64_t)j * M);
-    double re = 0.0, im = 0.0;
-    for (int s = 0; s < nsplit; ++s) {
-        const cx<T> v = part[(int64_t)s * M * N + idx];
-        re += (double)v.re;
-        im += (double)v.im;
+    const int64_t ss = (int64_t)M * N;
+    double r4[4] = {0.0, 0.0, 0.0, 0.0}, i4[4] = {0.0, 0.0, 0.0, 0.0};   // four independent chains
+    int s = 0;
+    for (; s + 3 < nsplit; s += 4) {
+        cx<T> v[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) v[u] = part[(int64_t)(s + u) * ss + idx];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            r4[u] += (double)v[u].re;
+            i4[u] += (double)v[u].im;
+        }
     }
+    for (int u = 0; s < nsplit; ++s, ++u) {
+        const cx<T> v = part[(int64_t)s * ss + idx];
+        r4[u] += (double)v.re;
+        i4[u] += (double)v.im;
+    }
+    double re = (r4[0] + r4[1]) + (r4[2] + r4[3]), im = (i4[0] + i4[1]) + (i4[2] + i4[3]);
     cx<T> *c = C + (int64_t)j * ldc + i;
     if (beta != 0.0) {
         re = alpha * re + beta * (double)c->re;
@@ -152,24 +167,54 @@ __global__ void k_reduce(int M, int N, int nsplit, const cx<T> *__restrict__ par
 }
 
 // P[j][i] = sum_s part[s][j][i]; Q[j][i] = sum_t D_blk(i)[i - lo][t] P[j][lo + t]
-// One work-group per band j; P of the band is staged in LDS.
+// One work-group per band j. The splits are divided among G thread groups
+// (G M <= blockDim.x), each thread summing its splits in four independent
+// chains; the group sums are added in a fixed order, so the result does not
+// depend on timing. P of the band is then in LDS for the D blocks.
+constexpr int kRedThreads = 1024, kRedMaxGroups = 8;
+__host__ __device__ inline int reduce_groups(int M) {
+    return M <= 0 ? 1 : std::max(1, std::min(kRedMaxGroups, std::min(kRedThreads / M, 4096 / M)));
+}
+
 template <typename T>
-__global__ __launch_bounds__(256) void k_reduce_dapply(int M, int nsplit, const cx<T> *__restrict__ part, int N,
-                                                       const double *__restrict__ dmat, const int *__restrict__ blo,
-                                                       const int *__restrict__ bn, const int *__restrict__ bdoff,
-                                                       cx<T> *__restrict__ P, cx<T> *__restrict__ Q) {
+__global__ __launch_bounds__(kRedThreads) void k_reduce_dapply(int M, int nsplit, const cx<T> *__restrict__ part,
+                                                               int N, const double *__restrict__ dmat,
+                                                               const int *__restrict__ blo, const int *__restrict__ bn,
+                                                               const int *__restrict__ bdoff, cx<T> *__restrict__ P,
+                                                               cx<T> *__restrict__ Q) {
     extern __shared__ __align__(16) unsigned char smem[];
-    cx<double> *pl = reinterpret_cast<cx<double> *>(smem);
+    cx<double> *pl = reinterpret_cast<cx<double> *>(smem);   // [G][M] group sums, then the total in [0][M]
     const int j = blockIdx.x;
-    for (int i = threadIdx.x; i < M; i += blockDim.x) {
-        double re = 0.0, im = 0.0;
-        for (int s = 0; s < nsplit; ++s) {
-            const cx<T> v = part[((int64_t)s * N + j) * M + i];
-            re += (double)v.re;
-            im += (double)v.im;
+    const int G = reduce_groups(M);
+    const int64_t sstride = (int64_t)N * M;
+    for (int idx = threadIdx.x; idx < G * M; idx += blockDim.x) {
+        const int g = idx / M, i = idx - g * M;
+        const cx<T> *src = part + (int64_t)j * M + i;
+        double re[4] = {0.0, 0.0, 0.0, 0.0}, im[4] = {0.0, 0.0, 0.0, 0.0};
+        int s = g;
+        for (; s + 3 * G < nsplit; s += 4 * G) {
+            cx<T> v[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) v[u] = src[(int64_t)(s + u * G) * sstride];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                re[u] += (double)v[u].re;
+                im[u] += (double)v[u].im;
+            }
         }
-        pl[i] = cx<double>{re, im};
-        if (P) P[(int64_t)j * M + i] = cx<T>{(T)re, (T)im};
+        for (int u = 0; s < nsplit; s += G, ++u) {
+            const cx<T> v = src[(int64_t)s * sstride];
+            re[u] += (double)v.re;
+            im[u] += (double)v.im;
+        }
+        pl[idx] = cx<double>{(re[0] + re[1]) + (re[2] + re[3]), (im[0] + im[1]) + (im[2] + im[3])};
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < M; i += blockDim.x) {
+        cx<double> t = pl[i];
+        for (int g = 1; g < G; ++g) t = t + pl[g * M + i];
+        pl[i] = t;
+        if (P) P[(int64_t)j * M + i] = cx<T>{(T)t.re, (T)t.im};
     }
     __syncthreads();
     for (int i = threadIdx.x; i < M; i += blockDim.x) {
@@ -358,10 +403,10 @@ static int proj_dapply_t(int M, int N, int K, const void *Bm, int64_t ldb, const
     if (M <= 0 || N <= 0) return ABACUS_PW_OK;
     int ns;
     APW_TRY(cn_part<T>(M, N, K, Bm, ldb, psi, ldp, part, chunk_hint, &ns, st));
-    const size_t lds = (size_t)M * sizeof(cx<double>);
+    const size_t lds = (size_t)reduce_groups(M) * M * sizeof(cx<double>);
     if (lds > 64 * 1024) return set_error(ABACUS_PW_EBAD_SHAPE, "too many projectors for the D-apply stage");
     KernelTimer kt("reduce_dapply", st);
-    hipLaunchKernelGGL(k_reduce_dapply<T>, dim3(N), dim3(256), lds, st, M, ns, static_cast<const cx<T> *>(part), N,
+    hipLaunchKernelGGL(k_reduce_dapply<T>, dim3(N), dim3(kRedThreads), lds, st, M, ns, static_cast<const cx<T> *>(part), N,
                        dmat, blo, bn, bdoff, static_cast<cx<T> *>(P), static_cast<cx<T> *>(Q));
     return check_launch("reduce_dapply");
 }
@@ -399,10 +444,10 @@ int gemm_nn_f32_into_f64(int M, int G, int K, const void *A, int64_t lda, const 
 
 int reduce_dapply_f32(int M, int N, int nsplit, const void *part, const double *dmat, const int *blo, const int *bn,
                       const int *bdoff, void *Q, hipStream_t st) {
-    const size_t lds = (size_t)M * sizeof(cx<double>);
+    const size_t lds = (size_t)reduce_groups(M) * M * sizeof(cx<double>);
     if (lds > 64 * 1024) return set_error(ABACUS_PW_EBAD_SHAPE, "too many projectors for the D-apply stage");
     KernelTimer kt("reduce_dapply", st);
-    hipLaunchKernelGGL(k_reduce_dapply<float>, dim3(N), dim3(256), lds, st, M, nsplit, static_cast<const c32 *>(part),
+    hipLaunchKernelGGL(k_reduce_dapply<float>, dim3(N), dim3(kRedThreads), lds, st, M, nsplit, static_cast<const c32 *>(part),
                        N, dmat, blo, bn, bdoff, static_cast<c32 *>(nullptr), static_cast<c32 *>(Q));
     return check_launch("reduce_dapply");
 }
