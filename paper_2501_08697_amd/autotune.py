@@ -3,8 +3,8 @@
 Searches the library's tuning knobs (abacus_pw_set_tuning) for one problem and
 precision by coordinate descent: starting from the defaults, each knob in turn
 is swept over its candidate values with the others fixed, keeping the fastest;
-two sweeps. Each candidate is timed with HIP events over `reps` H psi calls
-after one warm-up call. The winner is cached in a JSON file keyed by the
+two sweeps. Each candidate is timed with HIP events as the best of three
+repetitions of `reps` H psi calls, after one warm-up call. The winner is cached in a JSON file keyed by the
 problem's shape (grid, sphere sizes, projectors, bands, precision); the cache
 path is ABACUS_PW_AUTOTUNE_CACHE or ~/.cache/abacus_pw/autotune.json.
 
@@ -45,17 +45,22 @@ def _apply(cfg):
                  cfg.get("overlap", 0))
 
 
-def _time(dp, x, y, nb, precision, reps):
+def _time(dp, x, y, nb, precision, reps, trials=3):
+    """Best over `trials` of the mean time of `reps` calls (the minimum filters out
+    interference, so that near-equal candidates are not ranked by noise)."""
     import torch
     B.apply_h(dp, x, precision, nb=nb, out=y)
     a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    a.record()
-    for _ in range(reps):
-        B.apply_h(dp, x, precision, nb=nb, out=y)
-    b.record()
-    torch.cuda.synchronize()
-    return a.elapsed_time(b) / reps
+    best = float("inf")
+    for _ in range(trials):
+        torch.cuda.synchronize()
+        a.record()
+        for _ in range(reps):
+            B.apply_h(dp, x, precision, nb=nb, out=y)
+        b.record()
+        torch.cuda.synchronize()
+        best = min(best, a.elapsed_time(b) / reps)
+    return best
 
 
 def tune(dp: B.DeviceProblem, x, nb: int | None = None, precision: int = B.FP64, reps: int = 10,

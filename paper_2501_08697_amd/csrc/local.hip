@@ -52,20 +52,24 @@ __device__ __forceinline__ void batch_block(const KDesc *kd, const BatchArgs &ba
 
 constexpr int kMaxT3 = 32;     // widest j3 tile of the x pass
 constexpr int kXBands = 4;     // bands per x-pass work-group
-constexpr int kYzThreads = 512; // threads of a y-z plane work-group
+// Threads of a y-z plane work-group. An FP64 plane in LDS allows one group per
+// CU, so up to N = 72 it runs 16 waves; larger planes need more registers per
+// thread than 1024 threads leave (128 VGPRs), and FP32 planes fit three groups
+// of 8 waves per CU, which measured faster than fewer, larger groups.
+template <int N, typename T> constexpr int yz_threads() { return sizeof(T) == 8 && N <= 72 ? 1024 : 512; }
 constexpr int kYzBandsDefault = 2; // bands per y-z plane work-group
 
-// Copy an N x N plane from LDS to global memory, kYzThreads threads, four
+// Copy an N x N plane from LDS to global memory, yz_threads<N, T>() threads, four
 // elements per thread in flight (LDS reads first, then the stores).
 template <int N, typename T> __device__ __forceinline__ void store_plane(const cx<T> *plane, cx<T> *out, int tid) {
-    constexpr int NN = N * N, U = 4;
-    for (int i0 = tid; i0 < NN; i0 += U * kYzThreads) {
+    constexpr int NN = N * N, U = 4, NT = yz_threads<N, T>();
+    for (int i0 = tid; i0 < NN; i0 += U * NT) {
         cx<T> v[U];
 #pragma unroll
-        for (int u = 0; u < U; ++u) v[u] = plane[min(i0 + u * kYzThreads, NN - 1)];
+        for (int u = 0; u < U; ++u) v[u] = plane[min(i0 + u * NT, NN - 1)];
 #pragma unroll
         for (int u = 0; u < U; ++u)
-            if (i0 + u * kYzThreads < NN) out[i0 + u * kYzThreads] = v[u];
+            if (i0 + u * NT < NN) out[i0 + u * NT] = v[u];
     }
 }
 
@@ -73,7 +77,7 @@ template <int N, typename T> __device__ __forceinline__ void store_plane(const c
 // once into registers; while band b transforms, the sphere values of band b+1
 // are already being fetched.
 template <int N, typename T, typename TIN>
-__global__ __launch_bounds__(kYzThreads) void k_yz_inv(const cx<TIN> *__restrict__ psi_all, const KDesc *__restrict__ kd,
+__global__ __launch_bounds__((yz_threads<N, T>())) void k_yz_inv(const cx<TIN> *__restrict__ psi_all, const KDesc *__restrict__ kd,
                                                        BatchArgs ba, const cx<T> *__restrict__ tw_g,
                                                        cx<T> *__restrict__ slab, int nslab, int bpw) {
     KDesc D;
@@ -85,7 +89,7 @@ __global__ __launch_bounds__(kYzThreads) void k_yz_inv(const cx<TIN> *__restrict
     const cx<TIN> *psi = psi_all + ba.nb_total * (D.pw_off - ba.off0) + (int64_t)ba.b0 * D.npw;
     const int64_t ldpsi = D.npw;
     slab += (int64_t)kk * ba.bbt * nslab * (int64_t)(N * N);
-    constexpr int MAXP = 8;   // sphere points per thread held in registers
+    constexpr int MAXP = 4096 / yz_threads<N, T>();   // sphere points per thread held in registers
     extern __shared__ __align__(16) unsigned char smem[];
     cx<T> *plane = reinterpret_cast<cx<T> *>(smem);
     cx<T> *tw = plane + N * N;
@@ -231,7 +235,7 @@ __global__ __launch_bounds__(256) void k_xpass(cx<T> *__restrict__ slab, int nsl
 // band's psi at the plane's sphere points (whose indices and |k+G|^2 are read
 // once for all bands).
 template <int N, typename T, typename TIO>
-__global__ __launch_bounds__(kYzThreads) void k_yz_fwd(const cx<T> *__restrict__ slab, int nslab,
+__global__ __launch_bounds__((yz_threads<N, T>())) void k_yz_fwd(const cx<T> *__restrict__ slab, int nslab,
                                                        const KDesc *__restrict__ kd, BatchArgs ba,
                                                        const cx<T> *__restrict__ tw_g, const cx<TIO> *__restrict__ psi_all,
                                                        cx<TIO> *__restrict__ hpsi_all, double inv_n, int bpw) {
@@ -247,7 +251,8 @@ __global__ __launch_bounds__(kYzThreads) void k_yz_fwd(const cx<T> *__restrict__
     cx<TIO> *hpsi = hpsi_all + koff;
     const int64_t ld = D.npw;
     slab += (int64_t)kk * ba.bbt * nslab * (int64_t)(N * N);
-    constexpr int MAXQ = (N * N + kYzThreads - 1) / kYzThreads;
+    constexpr int NT = yz_threads<N, T>();
+    constexpr int MAXQ = (N * N + NT - 1) / NT;
     extern __shared__ __align__(16) unsigned char smem[];
     cx<T> *plane = reinterpret_cast<cx<T> *>(smem);
     cx<T> *tw = plane + N * N;
@@ -261,7 +266,7 @@ __global__ __launch_bounds__(kYzThreads) void k_yz_fwd(const cx<T> *__restrict__
         const cx<T> *in = slab + ((int64_t)b0 * nslab + s) * (int64_t)(N * N);
 #pragma unroll
         for (int q = 0; q < MAXQ; ++q) {
-            const int i = tid + q * kYzThreads;
+            const int i = tid + q * NT;
             pre[q] = i < N * N ? in[i] : czero<T>();
         }
     }
@@ -283,7 +288,7 @@ __global__ __launch_bounds__(kYzThreads) void k_yz_fwd(const cx<T> *__restrict__
     for (int b = b0; b < b1; ++b) {
 #pragma unroll
         for (int q = 0; q < MAXQ; ++q) {
-            const int i = tid + q * kYzThreads;
+            const int i = tid + q * NT;
             if (i < N * N) plane[i] = pre[q];
         }
         __syncthreads();
@@ -296,7 +301,7 @@ __global__ __launch_bounds__(kYzThreads) void k_yz_fwd(const cx<T> *__restrict__
             const cx<T> *in = slab + ((int64_t)(b + 1) * nslab + s) * (int64_t)(N * N);
 #pragma unroll
             for (int q = 0; q < MAXQ; ++q) {
-                const int i = tid + q * kYzThreads;
+                const int i = tid + q * NT;
                 if (i < N * N) pre[q] = in[i];
             }
         }
@@ -573,7 +578,7 @@ static int launch_yz(bool inverse, const Plan &P, int k0, int nkb, const BatchAr
             once = true;
         }
         KernelTimer kt("yz_inv", st);
-        hipLaunchKernelGGL((k_yz_inv<N, T, TIO>), grid, dim3(kYzThreads), lds_full, st,
+        hipLaunchKernelGGL((k_yz_inv<N, T, TIO>), grid, dim3(yz_threads<N, T>()), lds_full, st,
                            static_cast<const cx<TIO> *>(psi), kd, ba, tw, static_cast<cx<T> *>(slab), P.nslab, bpw);
         return check_launch("yz_inv");
     }
@@ -583,7 +588,7 @@ static int launch_yz(bool inverse, const Plan &P, int k0, int nkb, const BatchAr
         once = true;
     }
     KernelTimer kt("yz_fwd", st);
-    hipLaunchKernelGGL((k_yz_fwd<N, T, TIO>), grid, dim3(kYzThreads), lds_full, st, static_cast<const cx<T> *>(slab),
+    hipLaunchKernelGGL((k_yz_fwd<N, T, TIO>), grid, dim3(yz_threads<N, T>()), lds_full, st, static_cast<const cx<T> *>(slab),
                        P.nslab, kd, ba, tw, static_cast<const cx<TIO> *>(psi), static_cast<cx<TIO> *>(hpsi),
                        1.0 / (double)P.N, bpw);
     return check_launch("yz_fwd");
