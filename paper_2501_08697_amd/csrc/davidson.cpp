@@ -15,8 +15,10 @@
 // norms (and the Cholesky status) once per iteration to steer the loop.
 //
 // Mixed modes: a first Davidson phase applies H in reduced precision (FP32
-// transforms and FP32 projector GEMMs, complex128 vectors), then an FP64
-// phase refines the Ritz vectors to tol with the FP64 H.
+// transforms, FP32 or BF16 projector GEMMs, complex128 vectors) and forms the
+// subspace matrix V^H H V with FP32 products (FP32 MFMA, FP64 split-K sum);
+// orthonormalisation, Cholesky, Rayleigh-Ritz and residual norms stay FP64.
+// Then an FP64 phase refines the Ritz vectors to tol with the FP64 H.
 #include <algorithm>
 #include <cmath>
 #include <vector>
@@ -141,7 +143,13 @@ int davidson_k(const abacus_pw_problem &p, Plan &P, int k, int hprec, int nb, z6
     APW_TRY(d2d(Xc, X, vb * nb, st));
     APW_TRY(cholqr_rows(nb, npw, Xc, Y, b, 1, st));
     APW_TRY(apply_h_k(p, P, k, hprec, nb, Xc, Wc, st, false));
-    APW_TRY(gemm_cn(0, nb, nb, npw, Xc, npw, Wc, npw, C, nb, 1.0, 0.0, b.part.ptr, 0, st));
+    // subspace projections V^H (H V): FP32 products in a reduced-precision phase, else FP64
+    auto project = [&](int M, int N, const z64 *A, const z64 *B, z64 *Cout, int ldc) -> int {
+        return hprec == ABACUS_PW_FP64 ? gemm_cn(0, M, N, npw, A, npw, B, npw, Cout, ldc, 1.0, 0.0, b.part.ptr, 0, st)
+                                       : gemm_cn_f32_of_f64(M, N, npw, A, npw, B, npw, Cout, ldc, 1.0, 0.0, b.part.ptr,
+                                                            0, st);
+    };
+    APW_TRY(project(nb, nb, Xc, Wc, C, nb));
     APW_TRY(dav_hs_append(0, nb, C, nb, Hs, nmax, st));
     APW_TRY(dav_copy_block(nb, Hs, nmax, Hw, nmax, st));
     z64 *rc = nullptr;
@@ -214,7 +222,7 @@ int davidson_k(const abacus_pw_problem &p, Plan &P, int k, int hprec, int nb, z6
         APW_TRY(cholqr_rows(m, npw, T, Y, b, 2, st));
         APW_TRY(apply_h_k(p, P, k, hprec, m, T, HT, st, false));
         const int n = nbasis + m;
-        APW_TRY(gemm_cn(0, n, m, npw, V, npw, HT, npw, C, n, 1.0, 0.0, b.part.ptr, 0, st));
+        APW_TRY(project(n, m, V, HT, C, n));
         APW_TRY(dav_hs_append(nbasis, m, C, n, Hs, nmax, st));
         APW_TRY(dav_copy_block(n, Hs, nmax, Hw, nmax, st));
         APW_TRY(rayleigh_ritz(n, nb, nmax, b, &rc, st));

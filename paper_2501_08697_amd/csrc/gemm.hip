@@ -50,9 +50,11 @@ constexpr int kGemmWaves = 2;
 
 // ----------------------------------------------------------------- CN ------
 // part[s][j][i] = sum over k in split s of conj(A[i][k]) B[j][k]
-template <typename T>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kGemmWaves))) void k_gemm_cn_part(int M, int N, int K, int kchunk, const cx<T> *__restrict__ A,
-                                                      int64_t lda, const cx<T> *__restrict__ B, int64_t ldb,
+// TS is the type operands are stored in; they are rounded to T while staged
+// (FP32 products of FP64 vectors for the reduced-precision subspace projection).
+template <typename T, typename TS = T>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kGemmWaves))) void k_gemm_cn_part(int M, int N, int K, int kchunk, const cx<TS> *__restrict__ A,
+                                                      int64_t lda, const cx<TS> *__restrict__ B, int64_t ldb,
                                                       cx<T> *__restrict__ part) {
     __shared__ cx<T> As[TM][KP];
     __shared__ cx<T> Bs[TN][KP];
@@ -75,8 +77,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kGemmWaves)
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
             const int gk = k0 + lk + q;
-            ra[q] = (gi < M && gk < ke) ? A[gi * lda + gk] : cx<T>{T(0), T(0)};
-            rb[q] = (gj < N && gk < ke) ? B[gj * ldb + gk] : cx<T>{T(0), T(0)};
+            ra[q] = (gi < M && gk < ke) ? cvt<T>(A[gi * lda + gk]) : cx<T>{T(0), T(0)};
+            rb[q] = (gj < N && gk < ke) ? cvt<T>(B[gj * ldb + gk]) : cx<T>{T(0), T(0)};
         }
     };
     load(kb);
@@ -130,8 +132,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kGemmWaves)
 }
 
 // C[j][i] = alpha * sum_s part[s][j][i] + beta * C[j][i]   (fixed summation order)
-template <typename T>
-__global__ void k_reduce(int M, int N, int nsplit, const cx<T> *__restrict__ part, cx<T> *__restrict__ C, int64_t ldc,
+template <typename T, typename TC = T>
+__global__ void k_reduce(int M, int N, int nsplit, const cx<T> *__restrict__ part, cx<TC> *__restrict__ C, int64_t ldc,
                          double alpha, double beta) {
     const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (idx >= (int64_t)M * N) return;
@@ -155,7 +157,7 @@ __global__ void k_reduce(int M, int N, int nsplit, const cx<T> *__restrict__ par
         i4[u] += (double)v.im;
     }
     double re = (r4[0] + r4[1]) + (r4[2] + r4[3]), im = (i4[0] + i4[1]) + (i4[2] + i4[3]);
-    cx<T> *c = C + (int64_t)j * ldc + i;
+    cx<TC> *c = C + (int64_t)j * ldc + i;
     if (beta != 0.0) {
         re = alpha * re + beta * (double)c->re;
         im = alpha * im + beta * (double)c->im;
@@ -163,7 +165,7 @@ __global__ void k_reduce(int M, int N, int nsplit, const cx<T> *__restrict__ par
         re *= alpha;
         im *= alpha;
     }
-    *c = cx<T>{(T)re, (T)im};
+    *c = cx<TC>{(TC)re, (TC)im};
 }
 
 // P[j][i] = sum_s part[s][j][i]; Q[j][i] = sum_t D_blk(i)[i - lo][t] P[j][lo + t]
@@ -364,7 +366,7 @@ size_t gemm_cn_part_bytes(int M, int N, int K, int elem_bytes, int chunk_hint) {
     return (size_t)ns * M * N * elem_bytes;
 }
 
-template <typename T>
+template <typename T, typename TS = T>
 static int cn_part(int M, int N, int K, const void *A, int64_t lda, const void *B, int64_t ldb, void *part,
                    int chunk_hint, int *nsplit, hipStream_t st) {
     int chunk;
@@ -372,22 +374,28 @@ static int cn_part(int M, int N, int K, const void *A, int64_t lda, const void *
     *nsplit = ns;
     dim3 grid(ceil_div(M, TM), ceil_div(N, TN), ns);
     KernelTimer kt("gemm_cn", st);
-    hipLaunchKernelGGL(k_gemm_cn_part<T>, grid, dim3(256), 0, st, M, N, K, chunk, static_cast<const cx<T> *>(A), lda,
-                       static_cast<const cx<T> *>(B), ldb, static_cast<cx<T> *>(part));
+    hipLaunchKernelGGL((k_gemm_cn_part<T, TS>), grid, dim3(256), 0, st, M, N, K, chunk, static_cast<const cx<TS> *>(A),
+                       lda, static_cast<const cx<TS> *>(B), ldb, static_cast<cx<T> *>(part));
     return check_launch("gemm_cn");
 }
 
-template <typename T>
+// T: arithmetic and partial sums; TS: storage of A, B and C.
+template <typename T, typename TS = T>
 static int gemm_cn_t(int M, int N, int K, const void *A, int64_t lda, const void *B, int64_t ldb, void *C,
                      int64_t ldc, double alpha, double beta, void *part, int chunk_hint, hipStream_t st) {
     if (M <= 0 || N <= 0) return ABACUS_PW_OK;
     int ns;
-    APW_TRY(cn_part<T>(M, N, K, A, lda, B, ldb, part, chunk_hint, &ns, st));
+    APW_TRY((cn_part<T, TS>(M, N, K, A, lda, B, ldb, part, chunk_hint, &ns, st)));
     const int64_t tot = (int64_t)M * N;
     KernelTimer kt("gemm_reduce", st);
-    hipLaunchKernelGGL(k_reduce<T>, dim3((unsigned)ceil_div64(tot, 256)), dim3(256), 0, st, M, N, ns,
-                       static_cast<const cx<T> *>(part), static_cast<cx<T> *>(C), ldc, alpha, beta);
+    hipLaunchKernelGGL((k_reduce<T, TS>), dim3((unsigned)ceil_div64(tot, 256)), dim3(256), 0, st, M, N, ns,
+                       static_cast<const cx<T> *>(part), static_cast<cx<TS> *>(C), ldc, alpha, beta);
     return check_launch("gemm_reduce");
+}
+
+int gemm_cn_f32_of_f64(int M, int N, int K, const void *A, int64_t lda, const void *B, int64_t ldb, void *C,
+                       int64_t ldc, double alpha, double beta, void *part, int chunk_hint, hipStream_t st) {
+    return gemm_cn_t<float, double>(M, N, K, A, lda, B, ldb, C, ldc, alpha, beta, part, chunk_hint, st);
 }
 
 int gemm_cn(int prec, int M, int N, int K, const void *A, int64_t lda, const void *B, int64_t ldb, void *C,

@@ -19,6 +19,12 @@ int proj_dapply(int prec, int M, int N, int K, const void *Bm, int64_t ldb, cons
                 int chunk_hint, hipStream_t st);
 
 // C[j*ldc + g] = alpha * sum_i A[j*lda + i] B[i*ldb + g] + beta * C[...],  j < M, g < G.
+// gemm_cn on complex128 A, B, C with FP32 products: the operands are rounded to
+// complex64 as they are staged, partial sums are FP32, the split-K sum and C are FP64
+// (the subspace projection of the reduced-precision Davidson phase).
+int gemm_cn_f32_of_f64(int M, int N, int K, const void *A, int64_t lda, const void *B, int64_t ldb, void *C,
+                       int64_t ldc, double alpha, double beta, void *part, int chunk_hint, hipStream_t st);
+
 int gemm_nn(int prec, int M, int G, int K, const void *A, int64_t lda, const void *B, int64_t ldb, void *C,
             int64_t ldc, double alpha, double beta, hipStream_t st);
 
