@@ -7,8 +7,9 @@ the same seeded inputs.
 
 The arithmetic lives in ``oracle.c`` (own mixed-radix FFT, H psi, explicit H
 matrix, adjoint); this module loads it with ctypes and holds the block
-Davidson driver (``davidson``), written with numpy's dense linear algebra as
-its library steps.
+Davidson driver (``davidson``) and the band-by-band conjugate-gradient
+eigensolver (``cg``), written with numpy's dense linear algebra as their
+library steps.
 
 Problems are duck-typed: any object with the attributes of the generator's
 ``Problem`` (lattice, fft, kpts, npw, miller, vloc, nproj, natom,
@@ -276,6 +277,100 @@ def davidson(prob, psi0=None, tol=1e-8, max_iter=100, ndim=2, nb=None):
             return apply_h(sub, rows.reshape(-1), nb=rows.shape[0]).reshape(rows.shape)
 
         e, x, r, it = davidson_k(hop, x0, kinetic(sub, 0), tol, max_iter, ndim)
+        eig[k], res[k], its[k] = e, r, it
+        out[nb * off[k]: nb * off[k + 1]] = x.reshape(-1)
+    return eig, out, res, its
+
+
+def cg_k(hop, psi0: np.ndarray, kin: np.ndarray, tol: float, max_iter: int, history: bool = False):
+    """Band-by-band preconditioned conjugate gradient for the lowest nb eigenpairs
+    (the CG figure of Sec. III.B), rows in, rows out. For band i:
+
+    1. project out bands 0 .. i-1 and normalise; p = H psi_i, lambda = <psi_i|p>.
+    2. Repeat until ||p - lambda psi_i|| < tol or max_iter steps:
+       r = p - lambda psi_i; g = K r (Teter-Payne-Allan K of the band's kinetic
+       energy); project out bands 0 .. i; Polak-Ribiere
+       gamma = max(0, Re<g_k|r_k - r_{k-1}> / Re<g_{k-1}|r_{k-1}>) (0 at the first
+       step); d = g + gamma d_prev; the step direction is d with psi_i projected
+       out, normalised (d itself, unnormalised, carries the recurrence);
+       h = H d_hat; theta minimises the Rayleigh quotient on span{psi_i, d_hat}:
+       theta = atan2(-2b, c - a) / 2, a = lambda, b = Re<p|d_hat>, c = <d_hat|h>;
+       psi_i = cos(theta) psi_i + sin(theta) d_hat, p likewise with h,
+       lambda = <psi_i|p>.
+    Returns (lambda [nb], psi [nb][npw], residual norms [nb], steps [nb]) and, with
+    history, the Rayleigh quotients of every band after each step.
+    """
+    nb, npw = psi0.shape
+    x = np.array(psi0, dtype=np.complex128, copy=True)
+    lam = np.empty(nb)
+    rn = np.empty(nb)
+    its = np.zeros(nb, dtype=np.int64)
+    hist = []
+    for i in range(nb):
+        if i > 0:
+            x[i] -= x[:i].T @ (x[:i].conj() @ x[i])
+        x[i] /= np.linalg.norm(x[i])
+        p = hop(x[i:i + 1])[0]
+        lv = float(np.vdot(x[i], p).real)
+        d = None
+        r_prev = None
+        gr_prev = 0.0
+        k = 0
+        seq = [lv]
+        while True:
+            r = p - lv * x[i]
+            rnorm = float(np.linalg.norm(r))
+            if rnorm < tol or k >= max_iter:
+                break
+            ek = float(np.sum(kin * np.abs(x[i]) ** 2))
+            g = tpa_preconditioner(kin, np.array([ek]))[0] * r
+            g -= x[:i + 1].T @ (x[:i + 1].conj() @ g)
+            gr = float(np.vdot(g, r).real)
+            if k == 0:
+                d = g
+            else:
+                gamma = max(0.0, (gr - float(np.vdot(g, r_prev).real)) / gr_prev)
+                d = g + gamma * d
+            dp = d - np.vdot(x[i], d) * x[i]
+            dh = dp / np.linalg.norm(dp)
+            h = hop(dh[None, :])[0]
+            a = lv
+            b = float(np.vdot(p, dh).real)
+            c = float(np.vdot(dh, h).real)
+            theta = 0.5 * np.arctan2(-2.0 * b, c - a)
+            ct, st = np.cos(theta), np.sin(theta)
+            x[i] = ct * x[i] + st * dh
+            p = ct * p + st * h
+            lv = float(np.vdot(x[i], p).real)
+            r_prev, gr_prev = r, gr
+            k += 1
+            seq.append(lv)
+        lam[i], rn[i], its[i] = lv, rnorm, k
+        hist.append(seq)
+    if history:
+        return lam, x, rn, its, hist
+    return lam, x, rn, its
+
+
+def cg(prob, psi0=None, tol=1e-8, max_iter=200, nb=None):
+    """Oracle band-by-band CG over every k-point; returns (eig [nk][nb], psi packed, resid, steps [nk][nb])."""
+    nb = prob.nb if nb is None else nb
+    psi0 = prob.psi if psi0 is None else psi0
+    off = np.concatenate([[0], np.cumsum(prob.npw)]).astype(np.int64)
+    nk = len(prob.npw)
+    eig = np.empty((nk, nb))
+    res = np.empty((nk, nb))
+    its = np.empty((nk, nb), dtype=np.int64)
+    out = np.empty(nb * int(off[-1]), dtype=np.complex128)
+    for k in range(nk):
+        sub = _single_k(prob, k)
+        npw = int(prob.npw[k])
+        x0 = np.asarray(psi0[nb * off[k]: nb * off[k + 1]]).reshape(nb, npw)
+
+        def hop(rows, sub=sub):
+            return apply_h(sub, rows.reshape(-1), nb=rows.shape[0]).reshape(rows.shape)
+
+        e, x, r, it = cg_k(hop, x0, kinetic(sub, 0), tol, max_iter)
         eig[k], res[k], its[k] = e, r, it
         out[nb * off[k]: nb * off[k + 1]] = x.reshape(-1)
     return eig, out, res, its
