@@ -13,7 +13,8 @@ residual, the roofline of the dominant kernel (per-kernel times from HIP events
 recorded on the library's stream during the timed region), and the FP64 CPU
 oracle timed on this host.
 
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-davidson]
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-davidson] [--no-cg]
+                      [--no-batched] [--no-autotune]
 """
 from __future__ import annotations
 
@@ -45,6 +46,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-davidson", action="store_true")
+    ap.add_argument("--no-cg", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--traffic-probe", action="store_true",
@@ -317,6 +319,8 @@ def main():
 
     if not args.no_davidson:
         out["davidson"] = davidson_times(B, W, dev)
+    if not args.no_cg:
+        out["cg_vs_davidson"] = cg_times(B, W, dev, out.get("davidson"))
     if not args.no_batched:
         out["batched_kpoints"] = batched_times(B, W, dev, max(5, args.steps // 4))
 
@@ -380,6 +384,24 @@ def batched_times(B, W, dev, steps):
     for name, ms in out.items():
         res[name + "_batched_graph"] = {"ms": ms, "band_applies_per_s": tot / (ms * 1e-3),
                                         "speedup_vs_fp64_per_kpoint": t_perk / ms}
+    return res
+
+
+def cg_times(B, W, dev, dav):
+    """Band-by-band preconditioned CG on the benchmark workload to the same 1e-8
+    residual, FP64, beside the Davidson time of the same run."""
+    import torch
+    prob = W.make_problem(WORKLOAD)
+    dp = B.DeviceProblem(prob, device=dev)
+    x = torch.from_numpy(prob.psi).to(dev)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    eig, r, its, st = B.cg(dp, x, tol=1e-8, max_iter=400)
+    dt = time.perf_counter() - t0
+    res = {"s_per_kpoint": dt / prob.nk, "steps_per_band_mean": float(its.mean()), "steps_per_band_max": int(its.max()),
+           "max_resid": float(r.max()), "converged": st == 0, "lowest": float(eig.min())}
+    if dav and "fp64" in dav and "s_per_kpoint" in dav["fp64"]:
+        res["davidson_speedup_over_cg"] = dt / prob.nk / dav["fp64"]["s_per_kpoint"]
     return res
 
 

@@ -134,6 +134,29 @@ int abacus_pw_apply_h(const abacus_pw_problem *p, int precision, int nb, const v
                       void *stream);
 
 /*
+ * Lowest nb eigenpairs of H at every k-point by band-by-band preconditioned
+ * conjugate gradients (the CG figure of Sec. III.B): band i is projected
+ * against bands 0..i-1 and normalised, then repeatedly moved along a
+ * Polak-Ribiere direction built from the Teter-Payne-Allan preconditioned
+ * residual (projected against bands 0..i), by the rotation that minimises its
+ * Rayleigh quotient, until ||H psi_i - eps_i psi_i|| < tol or max_iter steps.
+ * H is applied to one band at a time, in FP64.
+ *
+ * psi_inout device complex128 packed [k][nb][npw_k]: initial guess in, eigenvectors out
+ *           (orthonormal).
+ * eig       host float64 [nk][nb]: eigenvalues in band order (Ry).
+ * tol       residual tolerance per band.
+ * max_iter  maximum number of CG steps per band.
+ * iters     host int [nk][nb] (may be NULL): CG steps taken by each band.
+ * resid     host float64 [nk][nb] (may be NULL): final residual norms.
+ * Returns 0 when every band converged, ABACUS_PW_NOT_CONVERGED (+1) otherwise
+ * (outputs valid), or a negative code (ENULL_ARG, EBAD_SHAPE, EBAD_FFT_SIZE,
+ * EBAD_SPHERE, EBAD_D, ENONFINITE, EHIP). Synchronises `stream` before returning.
+ */
+int abacus_pw_cg(const abacus_pw_problem *p, int nb, void *psi_inout, double *eig, double tol, int max_iter,
+                 int *iters, double *resid, void *stream);
+
+/*
  * Lowest nb eigenpairs of H at every k-point by block Davidson (Sec. III.B
  * names Davidson as the eigensolver of the plane-wave code without its steps;
  * the steps below are the library's): residuals R = H Psi - Psi Lambda,

@@ -23,7 +23,7 @@ ERRORS = {
     -6: "ENONFINITE", -7: "EBAD_PRECISION", -8: "EHIP", -9: "ECHOLESKY", -10: "EINTERNAL",
 }
 
-EXPORTS = ["abacus_pw_apply_h", "abacus_pw_davidson", "abacus_pw_apply_h_backward", "abacus_pw_last_error",
+EXPORTS = ["abacus_pw_apply_h", "abacus_pw_davidson", "abacus_pw_cg", "abacus_pw_apply_h_backward", "abacus_pw_last_error",
            "abacus_pw_fft_supported", "abacus_pw_plan_reset", "abacus_pw_profile_enable",
            "abacus_pw_profile_read", "abacus_pw_set_tuning"]
 
@@ -58,6 +58,7 @@ def lib():
         L.abacus_pw_apply_h.argtypes = [P, i, i, vp, vp, vp]
         L.abacus_pw_apply_h_backward.argtypes = [P, i, i, vp, vp, vp, vp, vp, vp]
         L.abacus_pw_davidson.argtypes = [P, i, i, vp, vp, d, i, i, vp, vp, vp]
+        L.abacus_pw_cg.argtypes = [P, i, vp, vp, d, i, vp, vp, vp]
         L.abacus_pw_last_error.argtypes = [C.c_char_p, i]
         L.abacus_pw_fft_supported.argtypes = [i]
         L.abacus_pw_profile_enable.argtypes = [i]
@@ -179,6 +180,19 @@ def davidson(dp: DeviceProblem, psi, tol=1e-8, max_iter=100, ndim=2, precision: 
     st = check(lib().abacus_pw_davidson(C.byref(cp), int(precision), int(nb), psi.data_ptr(), eig.ctypes.data,
                                         float(tol), int(max_iter), int(ndim), its.ctypes.data, res.ctypes.data,
                                         _stream(stream)))
+    return eig, res, its, st
+
+
+def cg(dp: DeviceProblem, psi, tol=1e-8, max_iter=200, nb: int | None = None, stream=None):
+    """Band-by-band preconditioned CG; psi (complex128) is updated in place.
+    Returns (eig [nk][nb], resid [nk][nb], steps [nk][nb], status)."""
+    nb = dp.prob.nb if nb is None else nb
+    eig = np.zeros((dp.nk, nb))
+    res = np.zeros((dp.nk, nb))
+    its = np.zeros((dp.nk, nb), dtype=np.int32)
+    cp = dp.c()
+    st = check(lib().abacus_pw_cg(C.byref(cp), int(nb), psi.data_ptr(), eig.ctypes.data, float(tol), int(max_iter),
+                                  its.ctypes.data, res.ctypes.data, _stream(stream)))
     return eig, res, its, st
 
 

@@ -197,4 +197,18 @@ int abacus_pw_davidson(const abacus_pw_problem *p, int precision, int nb, void *
     });
 }
 
+int abacus_pw_cg(const abacus_pw_problem *p, int nb, void *psi_inout, double *eig, double tol, int max_iter,
+                 int *iters, double *resid, void *stream) {
+    return guarded([&]() -> int {
+        if (!psi_inout || !eig) return set_error(ABACUS_PW_ENULL_ARG, "psi_inout and eig are required");
+        if (nb < 1 || max_iter < 0) return set_error(ABACUS_PW_EBAD_SHAPE, "need nb >= 1, max_iter >= 0");
+        if (!(tol > 0.0)) return set_error(ABACUS_PW_EBAD_SHAPE, "tol must be > 0");
+        Plan *P = nullptr;
+        APW_TRY(get_plan(p, &P));
+        for (int k = 0; k < p->nk; ++k)
+            if (p->npw[k] < nb) return set_error(ABACUS_PW_EBAD_SHAPE, "nb exceeds the sphere size");
+        return cg_all(*p, *P, nb, psi_inout, eig, tol, max_iter, iters, resid, static_cast<hipStream_t>(stream));
+    });
+}
+
 }  // extern "C"

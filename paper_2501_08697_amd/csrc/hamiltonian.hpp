@@ -25,6 +25,10 @@ int apply_h_all(const abacus_pw_problem &p, Plan &P, int prec, int nb, const voi
 int apply_h_backward_all(const abacus_pw_problem &p, Plan &P, int prec, int nb, const void *psi, const void *dy,
                          void *grad_psi, double *grad_v, double *grad_d, hipStream_t st);
 
+// Band-by-band preconditioned CG (abacus_pw_cg).
+int cg_all(const abacus_pw_problem &p, Plan &P, int nb, void *psi, double *eig, double tol, int max_iter, int *iters,
+           double *resid, hipStream_t st);
+
 // Block Davidson (abacus_pw_davidson).
 int davidson_all(const abacus_pw_problem &p, Plan &P, int prec, int nb, void *psi, double *eig, double tol,
                  int max_iter, int ndim, int *iters, double *resid, hipStream_t st);
