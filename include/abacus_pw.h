@@ -161,9 +161,11 @@ int abacus_pw_cg(const abacus_pw_problem *p, int nb, void *psi_inout, double *ei
  * names Davidson as the eigensolver of the plane-wave code without its steps;
  * the steps below are the library's): residuals R = H Psi - Psi Lambda,
  * Teter-Payne-Allan preconditioned corrections for unconverged bands, two
- * classical Gram-Schmidt passes against the basis, Cholesky-QR, Rayleigh-Ritz
- * on the basis [Psi, T] (restarted to the Ritz vectors when it would exceed
- * ndim*nb columns).
+ * classical Gram-Schmidt passes against the locked vectors and the basis,
+ * Cholesky-QR, Rayleigh-Ritz on the basis [Psi, T]. When the basis would exceed
+ * ndim*nb columns it restarts from the Ritz vectors, and the bands already
+ * below tol are locked: their pairs are frozen and leave the Rayleigh-Ritz
+ * problem, which then keeps the lowest nb - (locked) pairs.
  *
  * psi_inout device complex128 packed [k][nb][npw_k]: initial guess in, Ritz vectors out
  *           (orthonormal).

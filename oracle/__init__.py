@@ -194,20 +194,26 @@ def cholqr(x: np.ndarray) -> np.ndarray:
 
 
 def davidson_k(hop, psi0: np.ndarray, kin: np.ndarray, tol: float, max_iter: int, ndim: int = 2,
-               drop: float = 1e-10):
+               drop: float = 1e-10, info: dict | None = None):
     """Lowest nb eigenpairs of the Hermitian operator hop (rows in, rows out).
 
     1. Cholesky-QR psi0; W = H psi; Rayleigh-Ritz.
     2. Repeat: residuals R = W - psi Lambda and their 2-norms; stop when all < tol.
-       Preconditioned corrections T = K (.) R for unconverged bands, projected
-       out of the basis twice (classical Gram-Schmidt, twice), columns whose
-       norm fell below ``drop`` of their pre-projection norm are dropped,
-       Cholesky-QR twice; append T and HT; Rayleigh-Ritz on the whole basis
-       and keep the lowest nb. When the basis would exceed ndim*nb it is
-       restarted to the current Ritz vectors.
-    Returns (eig, psi, resid, iters).
+       Preconditioned corrections T = K (.) R for unconverged bands. When the
+       basis would exceed ndim*nb vectors it is restarted to the current Ritz
+       vectors, and at that restart every band whose residual is already below
+       tol is locked: its Ritz pair is frozen and leaves the Rayleigh-Ritz
+       problem. T is projected out of the locked vectors and the basis twice
+       (classical Gram-Schmidt, twice), columns whose norm fell below ``drop`` of
+       their pre-projection norm are dropped, Cholesky-QR twice; append T and HT;
+       Rayleigh-Ritz on the whole basis keeping the lowest nb - (locked) pairs.
+    The result merges locked and active pairs in ascending order of their Ritz
+    values (a stable sort, locked pairs first on ties).
+    Returns (eig, psi, resid, iters); ``info``, when given, receives the number
+    of restarts and of locked bands.
     """
     nb = psi0.shape[0]
+    restarts = 0
     x = cholqr(psi0)
     w = hop(x)
     hs = _gram(x, w)
@@ -217,6 +223,8 @@ def davidson_k(hop, psi0: np.ndarray, kin: np.ndarray, tol: float, max_iter: int
     w = y.T @ w
     vb, hvb = x.copy(), w.copy()
     hsub = np.diag(lam).astype(np.complex128)
+    xl = np.zeros((0, x.shape[1]), dtype=np.complex128)   # locked Ritz vectors
+    lam_l, rn_l = np.zeros(0), np.zeros(0)
     iters = 0
     while True:
         r = w - lam[:, None] * x
@@ -227,11 +235,19 @@ def davidson_k(hop, psi0: np.ndarray, kin: np.ndarray, tol: float, max_iter: int
         ekin = np.sum(kin[None, :] * np.abs(x[act]) ** 2, axis=1)
         t = tpa_preconditioner(kin, ekin) * r[act]
         if vb.shape[0] + t.shape[0] > ndim * nb:
+            conv = np.nonzero(rn < tol)[0]
+            if conv.size:
+                xl = np.concatenate([xl, x[conv]])
+                lam_l = np.concatenate([lam_l, lam[conv]])
+                rn_l = np.concatenate([rn_l, rn[conv]])
+                x, w, lam = x[act], w[act], lam[act]
             vb, hvb = x.copy(), w.copy()
             hsub = np.diag(lam).astype(np.complex128)
+            restarts += 1
+        q = np.concatenate([xl, vb])
         n0 = np.linalg.norm(t, axis=1)
         for _ in range(2):
-            t = t - _gram(vb, t).T @ vb
+            t = t - _gram(q, t).T @ q
         keep = np.linalg.norm(t, axis=1) >= drop * n0
         t = t[keep]
         if t.shape[0] == 0:
@@ -249,13 +265,18 @@ def davidson_k(hop, psi0: np.ndarray, kin: np.ndarray, tol: float, max_iter: int
         blk = hn[nold:, nold:]
         hn[nold:, nold:] = 0.5 * (blk + blk.conj().T)
         hsub = hn
+        na = x.shape[0]
         theta, y = np.linalg.eigh(hsub)
-        y = y[:, :nb]
-        lam = theta[:nb]
+        y = y[:, :na]
+        lam = theta[:na]
         x = y.T @ vb
         w = y.T @ hvb
         iters += 1
-    return lam, x, rn, iters
+    if info is not None:
+        info.update(restarts=restarts, locked=xl.shape[0])
+    lam_all = np.concatenate([lam_l, lam])
+    order = np.argsort(lam_all, kind="stable")
+    return lam_all[order], np.concatenate([xl, x])[order], np.concatenate([rn_l, rn])[order], iters
 
 
 def davidson(prob, psi0=None, tol=1e-8, max_iter=100, ndim=2, nb=None):

@@ -4,11 +4,13 @@
 //  1. Cholesky-QR of the initial block X; W = H X; Rayleigh-Ritz on span(X).
 //  2. Repeat: residuals R = W - X Lambda and their FP64 norms; stop when every
 //     norm < tol. Teter-Payne-Allan preconditioned corrections for the
-//     unconverged bands, two classical Gram-Schmidt passes against the basis,
+//     unconverged bands. When the basis would exceed ndim * nb vectors it
+//     restarts from the current Ritz vectors and locks the bands that have
+//     converged (their pairs leave the Rayleigh-Ritz problem). Two classical
+//     Gram-Schmidt passes against the locked vectors and the basis,
 //     corrections whose norm fell below 1e-10 of their pre-projection norm are
 //     dropped, Cholesky-QR twice; append T and H T to the basis; Rayleigh-Ritz
-//     on the whole basis keeping the lowest nb. When the basis would exceed
-//     ndim * nb vectors it restarts from the current Ritz vectors.
+//     on the whole basis keeping the lowest nb - (locked) pairs.
 //
 // Every vector operation runs on the device: GEMMs on MFMA, Cholesky and the
 // Hermitian eigensolver in FP64 (dense.hip). The host only reads the residual
@@ -34,7 +36,7 @@ namespace apw {
 namespace {
 
 struct Buffers {
-    DeviceBuffer V, HV, Xc, Wc, R, Y, Hs, Hw, coef, C, G, Linv, part, theta, rn2, ek, n0, n1, act, info, heev;
+    DeviceBuffer V, HV, Xc, Wc, R, Y, Hs, Hw, coef, C, G, Linv, part, theta, rn2, ek, n0, n1, act, idx, info, heev;
 };
 
 int d2h(void *dst, const void *src, size_t bytes, hipStream_t st) {
@@ -107,6 +109,12 @@ struct Result {
 // One Davidson phase at k-point k on the [nb][npw] block X (in/out).
 // hprec: precision of H. stagnation > 0 stops the phase early when the largest
 // residual has not dropped below 0.7 of its best value for that many iterations.
+//
+// Locking: at each restart, bands whose residual is below tol leave the
+// Rayleigh-Ritz problem. Their vectors stay fixed as the first nl rows of V,
+// corrections are orthogonalised against them together with the basis that
+// follows them in V, and Rayleigh-Ritz keeps the lowest nA = nb - nl pairs.
+// The output merges both sets in ascending order of their Ritz values.
 int davidson_k(const abacus_pw_problem &p, Plan &P, int k, int hprec, int nb, z64 *X, Buffers &b, double tol,
                int max_iter, int ndim, int stagnation, std::vector<double> &theta_h, std::vector<double> &rn_h,
                Result &res, hipStream_t st) {
@@ -114,7 +122,8 @@ int davidson_k(const abacus_pw_problem &p, Plan &P, int k, int hprec, int nb, z6
     const double *kin = P.k[k].kin;
     if (nmax > kMaxSub) return set_error(ABACUS_PW_EBAD_SHAPE, "ndim * nb exceeds the device eigensolver limit (1024)");
     const size_t vb = sizeof(z64) * (size_t)npw;
-    APW_TRY(b.V.ensure(vb * nmax));
+    const int vrows = nmax + nb;   // locked rows (at most nb - 1), then the basis
+    APW_TRY(b.V.ensure(vb * vrows));
     APW_TRY(b.HV.ensure(vb * nmax));
     APW_TRY(b.Xc.ensure(vb * nb));
     APW_TRY(b.Wc.ensure(vb * nb));
@@ -123,16 +132,17 @@ int davidson_k(const abacus_pw_problem &p, Plan &P, int k, int hprec, int nb, z6
     APW_TRY(b.Hs.ensure(sizeof(z64) * (size_t)nmax * nmax));
     APW_TRY(b.Hw.ensure(sizeof(z64) * (size_t)nmax * nmax));
     APW_TRY(b.coef.ensure(sizeof(z64) * (size_t)nb * nmax));
-    APW_TRY(b.C.ensure(sizeof(z64) * (size_t)nmax * nb));
+    APW_TRY(b.C.ensure(sizeof(z64) * (size_t)vrows * nb));
     APW_TRY(b.G.ensure(sizeof(z64) * (size_t)nb * nb));
     APW_TRY(b.Linv.ensure(sizeof(z64) * (size_t)nb * nb));
-    APW_TRY(b.part.ensure(std::max(gemm_cn_part_bytes(nmax, nb, npw, 16, 0), gemm_cn_part_bytes(nb, nb, npw, 16, 0))));
+    APW_TRY(b.part.ensure(std::max(gemm_cn_part_bytes(vrows, nb, npw, 16, 0), gemm_cn_part_bytes(nb, nb, npw, 16, 0))));
     APW_TRY(b.theta.ensure(sizeof(double) * nmax));
     APW_TRY(b.rn2.ensure(sizeof(double) * nb));
     APW_TRY(b.ek.ensure(sizeof(double) * nb));
     APW_TRY(b.n0.ensure(sizeof(double) * nb));
     APW_TRY(b.n1.ensure(sizeof(double) * nb));
     APW_TRY(b.act.ensure(sizeof(int) * nb));
+    APW_TRY(b.idx.ensure(sizeof(int) * nb));
     APW_TRY(b.info.ensure(sizeof(int)));
     APW_TRY(b.heev.ensure(heev_scratch_bytes(nmax)));
     z64 *V = b.V.as<z64>(), *HV = b.HV.as<z64>(), *Xc = b.Xc.as<z64>(), *Wc = b.Wc.as<z64>(), *R = b.R.as<z64>();
@@ -159,22 +169,26 @@ int davidson_k(const abacus_pw_problem &p, Plan &P, int k, int hprec, int nb, z6
     APW_TRY(d2d(Xc, V, vb * nb, st));
     APW_TRY(d2d(Wc, HV, vb * nb, st));
     APW_TRY(dav_hs_diag(nb, theta, Hs, nmax, st));
-    int nbasis = nb;
+    int nbasis = nb;   // basis rows, stored after the nl locked rows of V
+    int nA = nb, nl = 0;
+    std::vector<double> thL, rnL, thA(nb);
 
     std::vector<double> rn2(nb), n0(nb), n1(nb);
-    std::vector<int> act, keep;
+    std::vector<int> act, conv, keep;
     double best = INFINITY;
     int since_best = 0;
     res = Result{};
     for (;;) {
-        APW_TRY(dav_resid(nb, npw, Xc, Wc, theta, kin, R, b.rn2.as<double>(), b.ek.as<double>(), st));
-        APW_TRY(d2h(rn2.data(), b.rn2.ptr, sizeof(double) * nb, st));
+        z64 *Vb = V + (size_t)nl * npw;
+        APW_TRY(dav_resid(nA, npw, Xc, Wc, theta, kin, R, b.rn2.as<double>(), b.ek.as<double>(), st));
+        APW_TRY(d2h(rn2.data(), b.rn2.ptr, sizeof(double) * nA, st));
         act.clear();
+        conv.clear();
         double worst = 0.0;
-        for (int n = 0; n < nb; ++n) {
+        for (int n = 0; n < nA; ++n) {
             const double r = std::sqrt(rn2[n]);
             worst = std::max(worst, r);
-            if (!(r < tol)) act.push_back(n);
+            (r < tol ? conv : act).push_back(n);
         }
         if (act.empty()) {
             res.converged = true;
@@ -191,18 +205,50 @@ int davidson_k(const abacus_pw_problem &p, Plan &P, int k, int hprec, int nb, z6
         }
         int m = (int)act.size();
         APW_TRY(h2d(b.act.ptr, act.data(), sizeof(int) * m, st));
-        if (nbasis + m > nmax) {
-            APW_TRY(d2d(V, Xc, vb * nb, st));
-            APW_TRY(d2d(HV, Wc, vb * nb, st));
-            APW_TRY(dav_hs_diag(nb, theta, Hs, nmax, st));
-            nbasis = nb;
+        const bool restart = nbasis + m > nmax;
+        z64 *T;
+        if (restart && !conv.empty()) {
+            // lock the converged bands: their vectors join the locked rows, the
+            // active ones become the new basis
+            const int nc = (int)conv.size();
+            APW_TRY(dav_precond(m, npw, b.act.as<int>(), R, kin, b.ek.as<double>(), Y, st));
+            APW_TRY(h2d(b.idx.ptr, conv.data(), sizeof(int) * nc, st));
+            APW_TRY(dav_gather_rows(nc, npw, b.idx.as<int>(), Xc, Vb, st));
+            Vb = V + (size_t)(nl + nc) * npw;
+            APW_TRY(dav_gather_rows(m, npw, b.act.as<int>(), Xc, Vb, st));
+            APW_TRY(dav_gather_rows(m, npw, b.act.as<int>(), Wc, HV, st));
+            APW_TRY(d2d(Xc, Vb, vb * m, st));
+            APW_TRY(d2d(Wc, HV, vb * m, st));
+            APW_TRY(d2h(thA.data(), theta, sizeof(double) * nA, st));
+            for (int i : conv) {
+                thL.push_back(thA[i]);
+                rnL.push_back(std::sqrt(rn2[i]));
+            }
+            std::vector<double> th_new(m);
+            for (int i = 0; i < m; ++i) th_new[i] = thA[act[i]];
+            APW_TRY(h2d(theta, th_new.data(), sizeof(double) * m, st));
+            nl += nc;
+            nA = m;
+            nbasis = m;
+            APW_TRY(dav_hs_diag(nA, theta, Hs, nmax, st));
+            T = Vb + (size_t)nbasis * npw;
+            APW_TRY(d2d(T, Y, vb * m, st));
+        } else {
+            if (restart) {
+                APW_TRY(d2d(Vb, Xc, vb * nA, st));
+                APW_TRY(d2d(HV, Wc, vb * nA, st));
+                APW_TRY(dav_hs_diag(nA, theta, Hs, nmax, st));
+                nbasis = nA;
+            }
+            T = Vb + (size_t)nbasis * npw;
+            APW_TRY(dav_precond(m, npw, b.act.as<int>(), R, kin, b.ek.as<double>(), T, st));
         }
-        z64 *T = V + (size_t)nbasis * npw, *HT = HV + (size_t)nbasis * npw;
-        APW_TRY(dav_precond(m, npw, b.act.as<int>(), R, kin, b.ek.as<double>(), T, st));
+        z64 *HT = HV + (size_t)nbasis * npw;
+        const int north = nl + nbasis;   // locked rows and basis, contiguous in V
         APW_TRY(dav_row_norm2(m, npw, T, b.n0.as<double>(), st));
         for (int pass = 0; pass < 2; ++pass) {
-            APW_TRY(gemm_cn(0, nbasis, m, npw, V, npw, T, npw, C, nbasis, 1.0, 0.0, b.part.ptr, 0, st));
-            APW_TRY(gemm_nn(0, m, npw, nbasis, C, nbasis, V, npw, T, npw, -1.0, 1.0, st));
+            APW_TRY(gemm_cn(0, north, m, npw, V, npw, T, npw, C, north, 1.0, 0.0, b.part.ptr, 0, st));
+            APW_TRY(gemm_nn(0, m, npw, north, C, north, V, npw, T, npw, -1.0, 1.0, st));
         }
         APW_TRY(dav_row_norm2(m, npw, T, b.n1.as<double>(), st));
         APW_TRY(d2h(n0.data(), b.n0.ptr, sizeof(double) * m, st));
@@ -222,20 +268,42 @@ int davidson_k(const abacus_pw_problem &p, Plan &P, int k, int hprec, int nb, z6
         APW_TRY(cholqr_rows(m, npw, T, Y, b, 2, st));
         APW_TRY(apply_h_k(p, P, k, hprec, m, T, HT, st, false));
         const int n = nbasis + m;
-        APW_TRY(project(n, m, V, HT, C, n));
+        APW_TRY(project(n, m, Vb, HT, C, n));
         APW_TRY(dav_hs_append(nbasis, m, C, n, Hs, nmax, st));
         APW_TRY(dav_copy_block(n, Hs, nmax, Hw, nmax, st));
-        APW_TRY(rayleigh_ritz(n, nb, nmax, b, &rc, st));
-        APW_TRY(gemm_nn(0, nb, npw, n, rc, nmax, V, npw, Xc, npw, 1.0, 0.0, st));
-        APW_TRY(gemm_nn(0, nb, npw, n, rc, nmax, HV, npw, Wc, npw, 1.0, 0.0, st));
+        APW_TRY(rayleigh_ritz(n, nA, nmax, b, &rc, st));
+        APW_TRY(gemm_nn(0, nA, npw, n, rc, nmax, Vb, npw, Xc, npw, 1.0, 0.0, st));
+        APW_TRY(gemm_nn(0, nA, npw, n, rc, nmax, HV, npw, Wc, npw, 1.0, 0.0, st));
         nbasis = n;
         ++res.iters;
     }
-    APW_TRY(d2d(X, Xc, vb * nb, st));
-    theta_h.assign(nb, 0.0);
-    APW_TRY(d2h(theta_h.data(), theta, sizeof(double) * nb, st));
-    rn_h.resize(nb);
-    for (int n = 0; n < nb; ++n) rn_h[n] = std::sqrt(rn2[n]);
+    // Ritz pairs of the active block; with locked bands, merge both sets in
+    // ascending order of their Ritz values
+    APW_TRY(d2h(thA.data(), theta, sizeof(double) * nA, st));
+    theta_h.assign(thL.begin(), thL.end());
+    rn_h.assign(rnL.begin(), rnL.end());
+    for (int n = 0; n < nA; ++n) {
+        theta_h.push_back(thA[n]);
+        rn_h.push_back(std::sqrt(rn2[n]));
+    }
+    if (nl == 0) {
+        APW_TRY(d2d(X, Xc, vb * nb, st));
+    } else {
+        std::vector<int> perm(nb);
+        for (int i = 0; i < nb; ++i) perm[i] = i;
+        std::stable_sort(perm.begin(), perm.end(), [&](int a, int c) { return theta_h[a] < theta_h[c]; });
+        z64 *Vb = V + (size_t)nl * npw;
+        APW_TRY(d2d(Vb, Xc, vb * nA, st));
+        APW_TRY(h2d(b.idx.ptr, perm.data(), sizeof(int) * nb, st));
+        APW_TRY(dav_gather_rows(nb, npw, b.idx.as<int>(), V, X, st));
+        std::vector<double> ts(nb), rs(nb);
+        for (int i = 0; i < nb; ++i) {
+            ts[i] = theta_h[perm[i]];
+            rs[i] = rn_h[perm[i]];
+        }
+        theta_h.swap(ts);
+        rn_h.swap(rs);
+    }
     return ABACUS_PW_OK;
 }
 

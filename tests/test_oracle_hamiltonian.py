@@ -225,3 +225,29 @@ def test_davidson_free_electron_closed_form():
     kin = np.sort(kinetic_closed_form(p, 0))
     eig, psi, res, it = oracle.davidson(p, tol=1e-12, max_iter=100)
     np.testing.assert_allclose(eig[0], kin[:7], atol=1e-12)
+
+
+def test_davidson_locking_matches_dense():
+    """Bands locked at restarts stay eigenpairs; the active ones converge in their complement.
+
+    A projection of the corrections that missed the locked vectors would let active
+    bands converge onto locked eigenpairs (repeated eigenvalues), and a wrong merge
+    would break the ascending order: both fail the dense comparison.
+    """
+    p = tiny(nb=8, ecut=12.0, kfrac=((0.1, 0.0, 0.2),), lmax=2, natom=2, fft=16)
+    h = oracle.dense_h(p, 0)
+    ev = np.linalg.eigvalsh(h)[: p.nb]
+    sub = oracle._single_k(p, 0)
+
+    def hop(rows):
+        return oracle.apply_h(sub, rows.reshape(-1), nb=rows.shape[0]).reshape(rows.shape)
+
+    info = {}
+    eig, x, res, it = oracle.davidson_k(hop, p.psi.reshape(p.nb, -1), oracle.kinetic(sub, 0), 1e-11, 300, 2,
+                                        info=info)
+    assert info["locked"] > 0 and info["restarts"] > 0
+    np.testing.assert_allclose(eig, ev, atol=1e-12)
+    assert np.max(np.abs(x.conj() @ x.T - np.eye(p.nb))) < 1e-12
+    r = np.linalg.norm(x @ h.T - eig[:, None] * x, axis=1)
+    assert np.max(r) < 1e-11
+    np.testing.assert_allclose(r, res, atol=1e-13)
