@@ -1,4 +1,4 @@
-"""FP64 CPU oracle for the plane-wave H psi, its adjoint, and block Davidson.
+"""FP64 CPU oracle for the plane-wave H psi, its adjoint, the band density, and block Davidson.
 
 TEST INFRASTRUCTURE ONLY: this package is used by ``tests/``, by the smoke
 check and by the benchmark's CPU-baseline leg. The GPU library never imports,
@@ -6,7 +6,7 @@ links or calls it, and it shares no code with the GPU library; both only read
 the same seeded inputs.
 
 The arithmetic lives in ``oracle.c`` (own mixed-radix FFT, H psi, explicit H
-matrix, adjoint); this module loads it with ctypes and holds the block
+matrix, adjoint, band density); this module loads it with ctypes and holds the block
 Davidson driver (``davidson``) and the band-by-band conjugate-gradient
 eigensolver (``cg``), written with numpy's dense linear algebra as their
 library steps.
@@ -63,6 +63,7 @@ def lib():
         _lib.oracle_kinetic.argtypes = [P, i, vp]
         _lib.oracle_dense_h.argtypes = [P, i, i, vp]
         _lib.oracle_apply_h_backward.argtypes = [P, i, vp, vp, vp, vp, vp]
+        _lib.oracle_density.argtypes = [P, i, vp, vp, vp]
         _lib.oracle_num_threads.restype = i
     return _lib
 
@@ -159,6 +160,20 @@ def apply_h_backward(prob, psi, dy, nb=None, vloc=None, dmat=None, want=("psi", 
     gd = np.empty(np.asarray(prob.dmat).size) if "d" in want else None
     lib().oracle_apply_h_backward(C.byref(b.s), nb, _ptr(x), _ptr(g), _ptr(gp), _ptr(gv), _ptr(gd))
     return gp, gv, gd
+
+
+def density(prob, psi, occ, nb=None):
+    """rho(r_j) = sum_{k,n} occ[k][n] |psi_nk(r_j)|^2 on the [N1][N2][N3] grid, with psi_nk(r)
+    the unnormalised inverse transform of the coefficients (the k-weighted orbital density of
+    Sec. III.C; occ carries the k weight times the occupation)."""
+    nb = prob.nb if nb is None else nb
+    b = _Bound(prob)
+    x = np.ascontiguousarray(psi, dtype=np.complex128)
+    w = np.ascontiguousarray(occ, dtype=np.float64).reshape(-1)
+    assert x.size == nb * int(np.sum(prob.npw)) and w.size == nb * len(prob.npw)
+    rho = np.empty(tuple(prob.fft))
+    lib().oracle_density(C.byref(b.s), nb, _ptr(x), _ptr(w), _ptr(rho))
+    return rho
 
 
 # --------------------------------------------------------------------------

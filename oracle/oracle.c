@@ -443,4 +443,50 @@ void oracle_apply_h_backward(const oracle_problem *p, int nb, const cplx *psi, c
     free(gd_part);
 }
 
+/*
+ * Electron density on the grid: the k-weighted sum over orbitals of the squared
+ * modulus of each orbital's real-space values, as in the plane-wave density of
+ * Sec. III.C (the e^{ik.r} factor has modulus one and drops out), written with
+ * the unnormalised transform of the coefficients (no 1/Omega):
+ *   rho(r_j) = sum_{k,n} occ[k][n] |psi_nk(r_j)|^2,
+ *   psi_nk(r_j) = sum_{G in S_k} c_nk(G) exp(+i G.r_j)   (inverse transform of the
+ *   coefficients scattered to the grid, Miller index m -> m mod N).
+ * occ holds the weight of each band (k-point weight times occupation).
+ * rho is overwritten.
+ */
+void oracle_density(const oracle_problem *p, int nb, const cplx *psi, const double *occ, double *rho)
+{
+    const long N = (long)p->fft[0] * p->fft[1] * p->fft[2];
+    const int nthr = omp_get_max_threads();
+    double *part = (double *)calloc((size_t)N * (size_t)nthr, sizeof(double));
+    for (int k = 0; k < p->nk; ++k) {
+        const long off = pw_offset(p, k);
+        const int npw = p->npw[k];
+        const int *mil = p->miller + 3 * off;
+        #pragma omp parallel
+        {
+            const int t = omp_get_thread_num();
+            long m = maxdim(p->fft);
+            cplx *ga = (cplx *)malloc(sizeof(cplx) * (size_t)N);
+            cplx *out = (cplx *)malloc(sizeof(cplx) * (size_t)m);
+            cplx *work = (cplx *)malloc(sizeof(cplx) * (size_t)(2 * m + 1));
+            #pragma omp for schedule(static)
+            for (int n = 0; n < nb; ++n) {
+                const cplx *x = psi + (long)nb * off + (long)n * npw;
+                const double w = occ[(long)k * nb + n];
+                memset(ga, 0, sizeof(cplx) * (size_t)N);
+                for (int g = 0; g < npw; ++g) ga[grid_index(p->fft, mil + 3 * g)] = x[g];
+                fft3d_inplace(p->fft, +1, ga, NULL, out, work);
+                double *acc = part + (long)t * N;
+                for (long j = 0; j < N; ++j) acc[j] += w * (creal(ga[j]) * creal(ga[j]) + cimag(ga[j]) * cimag(ga[j]));
+            }
+            free(ga); free(out); free(work);
+        }
+    }
+    memset(rho, 0, sizeof(double) * (size_t)N);
+    for (int t = 0; t < nthr; ++t)
+        for (long j = 0; j < N; ++j) rho[j] += part[(long)t * N + j];
+    free(part);
+}
+
 int oracle_num_threads(void) { return omp_get_max_threads(); }

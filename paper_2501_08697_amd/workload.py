@@ -313,3 +313,12 @@ def tiny_config(a=6.0, ecut=8.0, fft=8, kfrac=_GAMMA, natom=2, lmax=1, nb=4, see
                 dfull=False, with_grad_inputs=False) -> Config:
     """A small custom configuration for tests."""
     return Config("tiny", a, ecut, fft, tuple(kfrac), natom, lmax, nb, seed, dfull, with_grad_inputs)
+
+
+def band_weights(prob, seed: int = 0) -> np.ndarray:
+    """Weights of the density sum, [nk][nb] float64: k-point weight 1/nk times an
+    occupation f_n ~ U(0, 2) drawn from its own stream (seed 1000 + seed), so the
+    problem's other draws are unchanged."""
+    rng = np.random.default_rng(1000 + seed)
+    nk = len(prob.npw)
+    return rng.uniform(0.0, 2.0, size=(nk, prob.nb)) / nk
