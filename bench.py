@@ -14,7 +14,7 @@ recorded on the library's stream during the timed region), and the FP64 CPU
 oracle timed on this host.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-davidson] [--no-cg]
-                      [--no-batched] [--no-autotune]
+                      [--no-batched] [--no-autotune] [--no-density]
 """
 from __future__ import annotations
 
@@ -49,6 +49,7 @@ def parse():
     ap.add_argument("--no-cg", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-density", action="store_true")
     ap.add_argument("--traffic-probe", action="store_true",
                     help="run a plain 256 MiB copy and a few H psi steps only (for counter collection)")
     return ap.parse_args()
@@ -317,6 +318,8 @@ def main():
         "tuning": tuning,
     }
 
+    if not args.no_density:
+        out["density"] = density_times(B, W, dev, prob, dp, x64, args.steps)
     if not args.no_davidson:
         out["davidson"] = davidson_times(B, W, dev)
     if not args.no_cg:
@@ -327,6 +330,64 @@ def main():
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(prob)
     print(json.dumps(out), flush=True)
+
+
+def density_times(B, W, dev, prob, dp, x, steps):
+    """Band density rho(r) = sum_n w_n |psi_n(r)|^2 of the benchmark's 128 bands on its 72^3 grid, FP64.
+
+    Per call: the y-z inverse passes (sphere -> slab planes) and one x pass that
+    transforms and accumulates (k_density_x), then the fixed-order sum of the
+    partial grids. The model bytes are the inverse half of the pruned 5-pass
+    local-term model plus rho written once: nb (cb N 2 (f_disk + f_slab) + cb npw) + 8 N.
+    k_density_x moves nb cb S (slab in) plus its partial grids (G = 8 of N doubles,
+    read and written once per band batch).
+    """
+    import torch
+    nb = prob.nb
+    occ = torch.from_numpy(W.band_weights(prob, 0)).to(dev)
+    rho = torch.empty(tuple(prob.fft), dtype=torch.float64, device=dev)
+    for _ in range(3):
+        B.density(dp, x, occ, out=rho)
+    torch.cuda.synchronize()
+    B.profile_read()
+    B.profile_enable(True)
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(steps):
+        B.density(dp, x, occ, out=rho)
+    b.record()
+    torch.cuda.synchronize()
+    B.profile_enable(False)
+    kern = B.profile_read()
+    ms_ev = a.elapsed_time(b) / steps
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(steps):
+        B.density(dp, x, occ, out=rho)
+    b.record()
+    torch.cuda.synchronize()
+    ms = a.elapsed_time(b) / steps
+    cb = 16
+    n1, n2, n3 = prob.fft
+    N = n1 * n2 * n3
+    model_b, _, f_disk, f_slab = local_model_bytes(prob)
+    npw = int(prob.npw[0])
+    model = nb * (cb * N * 2 * (f_disk + f_slab) + cb * npw) + 8 * N
+    m1 = prob.miller[:, 0]
+    S = (int(m1.max()) - int(m1.min()) + 1) * n2 * n3
+    rows = {}
+    for name, (n, tot) in kern.items():
+        rows[name] = {"launches_per_call": n / steps, "avg_ms": tot / n}
+    res = {"ms_per_call": ms, "ms_per_call_with_kernel_events": ms_ev, "band_densities_per_s": nb / (ms * 1e-3),
+           "model_bytes": model, "effective_GBs": model / (ms * 1e-3) / 1e9,
+           "frac_effective": model / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, "kernels": rows}
+    if "density_x" in rows:
+        r = rows["density_x"]
+        bands = nb / r["launches_per_call"]
+        by = bands * cb * S + 2 * 8 * 8 * N
+        r["alg_bytes"] = by
+        r["gbs"] = by / (r["avg_ms"] * 1e-3) / 1e9
+    return res
 
 
 def batched_times(B, W, dev, steps):
@@ -411,6 +472,9 @@ def davidson_times(B, W, dev):
     res = {}
     prob = W.make_problem(WORKLOAD)
     dp = B.DeviceProblem(prob, device=dev)
+    x = torch.from_numpy(prob.psi).to(dev)
+    B.apply_h(dp, x)   # plan and work space built outside the timed solves
+    torch.cuda.synchronize()
     for name, prec in (("fp64", B.FP64), ("mixed_fp32", B.MIXED_FP32)):
         x = torch.from_numpy(prob.psi).to(dev)
         torch.cuda.synchronize()

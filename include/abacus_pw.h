@@ -201,6 +201,25 @@ int abacus_pw_apply_h_backward(const abacus_pw_problem *p, int precision, int nb
                                const void *dY, void *grad_psi, double *grad_vloc, double *grad_dmat,
                                void *stream);
 
+/*
+ * Band density on the FFT grid. Sec. III.C forms the plane-wave density as a
+ * k-weighted sum, over orbitals, of the squared modulus of each orbital's
+ * real-space values (the e^{ik.r} factor has modulus one):
+ *   rho(r_j) = sum_{k,n} occ[k][n] |psi_nk(r_j)|^2,
+ *   psi_nk(r_j) = sum_{G in S_k} c_nk(G) exp(+i G.r_j)   (unnormalised inverse transform,
+ *                 Miller index m -> m mod N, no 1/Omega).
+ * psi       device, layout and type as in abacus_pw_apply_h (FP64: complex128; FP32: complex64,
+ *           with FP32 transforms and FP64 accumulation of the squared moduli).
+ * occ       device float64 [nk][nb]: weight of each band (k-point weight times occupation,
+ *           spin factor included); any real values.
+ * rho       device float64 [N1][N2][N3], overwritten.
+ * The sum over bands and k runs in a fixed order (repeatable bit for bit).
+ * Asynchronous. Errors: ENULL_ARG, EBAD_SHAPE, EBAD_PRECISION (MIXED modes), and those of
+ * abacus_pw_apply_h.
+ */
+int abacus_pw_density(const abacus_pw_problem *p, int precision, int nb, const void *psi, const double *occ,
+                      double *rho, void *stream);
+
 /* Message for the last error on the calling thread (truncated to size). Returns len. */
 int abacus_pw_last_error(char *buf, int size);
 

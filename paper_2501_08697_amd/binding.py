@@ -23,7 +23,8 @@ ERRORS = {
     -6: "ENONFINITE", -7: "EBAD_PRECISION", -8: "EHIP", -9: "ECHOLESKY", -10: "EINTERNAL",
 }
 
-EXPORTS = ["abacus_pw_apply_h", "abacus_pw_davidson", "abacus_pw_cg", "abacus_pw_apply_h_backward", "abacus_pw_last_error",
+EXPORTS = ["abacus_pw_apply_h", "abacus_pw_davidson", "abacus_pw_cg", "abacus_pw_apply_h_backward", "abacus_pw_density",
+           "abacus_pw_last_error",
            "abacus_pw_fft_supported", "abacus_pw_plan_reset", "abacus_pw_profile_enable",
            "abacus_pw_profile_read", "abacus_pw_set_tuning"]
 
@@ -58,6 +59,7 @@ def lib():
         L.abacus_pw_apply_h.argtypes = [P, i, i, vp, vp, vp]
         L.abacus_pw_apply_h_backward.argtypes = [P, i, i, vp, vp, vp, vp, vp, vp]
         L.abacus_pw_davidson.argtypes = [P, i, i, vp, vp, d, i, i, vp, vp, vp]
+        L.abacus_pw_density.argtypes = [P, i, i, vp, vp, vp, vp]
         L.abacus_pw_cg.argtypes = [P, i, vp, vp, d, i, vp, vp, vp]
         L.abacus_pw_last_error.argtypes = [C.c_char_p, i]
         L.abacus_pw_fft_supported.argtypes = [i]
@@ -167,6 +169,21 @@ def apply_h_backward(dp: DeviceProblem, psi, dy, precision: int = FP64, nb: int 
                                            None if gv is None else gv.data_ptr(),
                                            None if gd is None else gd.data_ptr(), _stream(stream)))
     return gp, gv, gd
+
+
+def density(dp: DeviceProblem, psi, occ, precision: int = FP64, nb: int | None = None, stream=None, out=None):
+    """rho [N1][N2][N3] float64 = sum_{k,n} occ[k][n] |psi_nk(r)|^2 (occ: [nk][nb], numpy or torch)."""
+    import torch
+    nb = dp.prob.nb if nb is None else nb
+    psi = psi.contiguous()
+    w = torch.as_tensor(occ, dtype=torch.float64).to(psi.device).contiguous()
+    if w.numel() != dp.nk * nb:
+        raise AbacusPwError(-2, f"occ must hold nk * nb = {dp.nk * nb} weights, got {w.numel()}")
+    rho = torch.empty(dp.fft, dtype=torch.float64, device=psi.device) if out is None else out
+    cp = dp.c()
+    check(lib().abacus_pw_density(C.byref(cp), int(precision), int(nb), psi.data_ptr(), w.data_ptr(), rho.data_ptr(),
+                                  _stream(stream)))
+    return rho
 
 
 def davidson(dp: DeviceProblem, psi, tol=1e-8, max_iter=100, ndim=2, precision: int = FP64, nb: int | None = None,

@@ -180,6 +180,19 @@ int abacus_pw_apply_h_backward(const abacus_pw_problem *p, int precision, int nb
     });
 }
 
+int abacus_pw_density(const abacus_pw_problem *p, int precision, int nb, const void *psi, const double *occ,
+                      double *rho, void *stream) {
+    return guarded([&]() -> int {
+        if (!psi || !occ || !rho) return set_error(ABACUS_PW_ENULL_ARG, "psi, occ and rho are required");
+        if (nb < 1) return set_error(ABACUS_PW_EBAD_SHAPE, "nb must be >= 1");
+        if (precision != ABACUS_PW_FP64 && precision != ABACUS_PW_FP32)
+            return set_error(ABACUS_PW_EBAD_PRECISION, "the density runs in FP64 or FP32");
+        Plan *P = nullptr;
+        APW_TRY(get_plan(p, &P));
+        return density_all(*p, *P, precision, nb, psi, occ, rho, static_cast<hipStream_t>(stream));
+    });
+}
+
 int abacus_pw_davidson(const abacus_pw_problem *p, int precision, int nb, void *psi_inout, double *eig, double tol,
                        int max_iter, int ndim, int *iters, double *resid, void *stream) {
     return guarded([&]() -> int {

@@ -6,6 +6,7 @@
 //   grad_D[a](i,j) = Re sum_{k,n} Q_in conj(P_jn),  P = B^H psi, Q = B^H dY
 // The grids are recomputed from psi and dY (nothing is kept from a forward
 // call). Band and k sums run in a fixed order, so results repeat bit for bit.
+// The band density shares the grid-gradient machinery (one transform per band).
 #include <algorithm>
 
 #include "gemm.hpp"
@@ -57,9 +58,34 @@ int apply_h_backward_all(const abacus_pw_problem &p, Plan &P, int prec, int nb, 
                                            kGradVGroups, first, st));
             first = 0;
         }
-        APW_TRY(local_gradv_finish(P, P.gradv_part.as<double>(), kGradVGroups, grad_v, st));
+        APW_TRY(local_sum_parts(P, P.gradv_part.as<double>(), kGradVGroups, 1.0 / (double)P.N, grad_v, st));
     }
     return ABACUS_PW_OK;
+}
+
+// Band density (abacus_pw_density): rho(r_j) = sum_{k,n} occ[k][n] |psi_nk(r_j)|^2, psi_nk(r)
+// the unnormalised inverse transform of the coefficients. Per band batch the y-z
+// inverse transforms of every k-point write slab planes, then one x pass
+// transforms them and adds the weighted squared moduli; the G partial grids are
+// summed in a fixed order at the end.
+int density_all(const abacus_pw_problem &p, Plan &P, int prec, int nb, const void *psi, const double *occ,
+                double *rho, hipStream_t st) {
+    (void)p;
+    const int fp = prec == ABACUS_PW_FP64 ? 0 : 1;
+    const int io = prec == ABACUS_PW_FP32 ? 1 : 0;
+    APW_TRY(local_supported(P, fp));
+    const int bb = default_band_batch(P, nb);
+    APW_TRY(P.slab.ensure(local_slab_bytes(P, fp, P.nk * bb)));
+    APW_TRY(P.gradv_part.ensure(sizeof(double) * (size_t)kGradVGroups * P.N));
+    int first = 1;
+    for (int b0 = 0; b0 < nb; b0 += bb) {
+        const int n = std::min(bb, nb - b0);
+        APW_TRY(local_inverse_planes(P, 0, P.nk, nb, b0, n, fp, io, psi, P.slab.ptr, st));
+        APW_TRY(local_density_accumulate(P, fp, P.slab.ptr, P.nk * n, occ, nb, b0, n, P.gradv_part.as<double>(),
+                                         kGradVGroups, first, st));
+        first = 0;
+    }
+    return local_sum_parts(P, P.gradv_part.as<double>(), kGradVGroups, 1.0, rho, st);
 }
 
 }  // namespace apw

@@ -24,6 +24,9 @@ int apply_h_all(const abacus_pw_problem &p, Plan &P, int prec, int nb, const voi
 // Adjoint of apply_h_all (abacus_pw_apply_h_backward).
 int apply_h_backward_all(const abacus_pw_problem &p, Plan &P, int prec, int nb, const void *psi, const void *dy,
                          void *grad_psi, double *grad_v, double *grad_d, hipStream_t st);
+// Band density rho(r_j) = sum_{k,n} occ[k][n] |psi_nk(r_j)|^2 (occ device [nk][nb]); rho overwritten.
+int density_all(const abacus_pw_problem &p, Plan &P, int prec, int nb, const void *psi, const double *occ,
+                double *rho, hipStream_t st);
 
 // Band-by-band preconditioned CG (abacus_pw_cg).
 int cg_all(const abacus_pw_problem &p, Plan &P, int nb, void *psi, double *eig, double tol, int max_iter, int *iters,

@@ -501,7 +501,94 @@ __global__ __launch_bounds__(256) void k_gradv_x(const cx<T> *__restrict__ slab_
     }
 }
 
-// grad_v[j] = (1/N) sum_{g < G} part[g][j]   (fixed order)
+// Band density: for one (j2, j3 tile) and the contiguous band range
+// [g bpw, (g + 1) bpw) of the batch, inverse x transforms of the psi planes
+// and acc(r) += w_b |psi_b(r)|^2, w_b = occ[k][b0 + b] for the virtual band
+// (k, b); part[g] holds the running sum (overwritten when first != 0). The
+// transform is the two-level one of k_xpass without its forward half: phase I
+// takes the B values of slots B ka + kb from HBM, inverse DFT_B, twiddle, to
+// LDS; phase F takes the A values of slots jb + B q, inverse DFT_A gives
+// psi(j1) at j1 = jb + B q, and the thread adds w |psi|^2 into its registers
+// for those A points. The next band's phase-I values are fetched as soon as
+// phase I has consumed the current ones; two barriers per band. Bands are
+// summed in a fixed order.
+template <int N1, typename T>
+__global__ __launch_bounds__(256) void k_density_x(const cx<T> *__restrict__ slab, int nslab, int N2, int N3, int T3,
+                                                   int nt3, int nbands, int bpw, const int *__restrict__ row_to_slab,
+                                                   const cx<T> *__restrict__ tw_g, const double *__restrict__ occ,
+                                                   int nb, int b0, int bbt, double *__restrict__ part, int first) {
+    constexpr int A = LdsSplit<N1>::A, B = LdsSplit<N1>::B;
+    extern __shared__ __align__(16) unsigned char smem[];
+    cx<T> *tile = reinterpret_cast<cx<T> *>(smem);       // [N1 slots][T3]
+    cx<T> *tw = tile + N1 * T3;
+    int *r2s = reinterpret_cast<int *>(tw + N1);
+    const int j2 = blockIdx.x / nt3, c0 = (blockIdx.x - j2 * nt3) * T3;
+    const int w3 = min(T3, N3 - c0);
+    const int g = blockIdx.y, bs = g * bpw, be = min(nbands, bs + bpw);
+    const int tid = threadIdx.x;
+    const int64_t plane = (int64_t)N2 * N3;
+    const int64_t bstride = (int64_t)nslab * plane;
+    for (int i = tid; i < N1; i += blockDim.x) {
+        tw[i] = tw_g[i];
+        r2s[i] = row_to_slab[i];
+    }
+    __syncthreads();
+    const int c = w3 > 0 ? tid % w3 : 0;
+    const int ka = tid / w3, jb = tid / w3;
+    const bool has_ka = tid < w3 * A, has_jb = tid < w3 * B;
+    const cx<T> *base = slab + (int64_t)j2 * N3 + c0 + c;
+    int64_t src[B];
+#pragma unroll
+    for (int kb = 0; kb < B; ++kb) {
+        const int sl = has_ka ? r2s[B * ka + kb] : -1;
+        src[kb] = sl >= 0 ? sl * plane : -1;
+    }
+    double acc[A];
+#pragma unroll
+    for (int q = 0; q < A; ++q) acc[q] = 0.0;
+    cx<T> pre[B];
+#pragma unroll
+    for (int kb = 0; kb < B; ++kb)
+        pre[kb] = (has_ka && src[kb] >= 0 && bs < be) ? base[bs * bstride + src[kb]] : czero<T>();
+    for (int b = bs; b < be; ++b) {
+        if (has_ka) {
+            cx<T> z[B];
+#pragma unroll
+            for (int kb = 0; kb < B; ++kb) z[kb] = pre[kb];
+            if (b + 1 < be) {
+#pragma unroll
+                for (int kb = 0; kb < B; ++kb)
+                    if (src[kb] >= 0) pre[kb] = base[(b + 1) * bstride + src[kb]];
+            }
+            RegDft<B, +1, T>::run(z);
+            tile[(B * ka) * T3 + c] = z[0];
+#pragma unroll
+            for (int q = 1; q < B; ++q) tile[(B * ka + q) * T3 + c] = cmul(z[q], tw[q * A + ka]);
+        }
+        __syncthreads();
+        if (has_jb) {
+            const int kk = b / bbt;
+            const double w = occ[(int64_t)kk * nb + b0 + (b - kk * bbt)];
+            cx<T> a[A];
+#pragma unroll
+            for (int q = 0; q < A; ++q) a[q] = tile[(jb + B * q) * T3 + c];
+            RegDft<A, +1, T>::run(a);
+#pragma unroll
+            for (int q = 0; q < A; ++q)
+                acc[q] += w * ((double)a[q].re * (double)a[q].re + (double)a[q].im * (double)a[q].im);
+        }
+        __syncthreads();
+    }
+    if (has_jb) {
+#pragma unroll
+        for (int q = 0; q < A; ++q) {
+            double *o = part + (int64_t)g * N1 * plane + (int64_t)(jb + B * q) * plane + (int64_t)j2 * N3 + c0 + c;
+            *o = first ? acc[q] : *o + acc[q];
+        }
+    }
+}
+
+// out[j] = scale * sum_{g < G} part[g][j]   (fixed order)
 __global__ void k_gradv_reduce(int64_t n, int G, const double *__restrict__ part, double *__restrict__ out, double inv_n) {
     for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < n; j += (int64_t)gridDim.x * blockDim.x) {
         double s = 0.0;
@@ -696,6 +783,24 @@ static int launch_gradv(const Plan &P, const void *sx, const void *sy, int nband
     return check_launch("gradv_x");
 }
 
+template <int N1, typename T>
+static int launch_density(const Plan &P, const void *slab, int nbands, const double *occ, int nb, int b0, int bbt,
+                          double *part, int G, int first, hipStream_t st) {
+    const int T3 = xpass_tile(N1, P.N3), nt3 = ceil_div(P.N3, T3);
+    const size_t lds = (size_t)(N1 * T3 + N1) * sizeof(cx<T>) + (size_t)N1 * sizeof(int);
+    static bool once = false;
+    if (!once) {
+        APW_TRY(allow_lds(k_density_x<N1, T>, kLdsLimit));
+        once = true;
+    }
+    const cx<T> *tw = static_cast<const cx<T> *>(sizeof(T) == 8 ? P.tw64[0] : P.tw32[0]);
+    KernelTimer kt("density_x", st);
+    hipLaunchKernelGGL((k_density_x<N1, T>), dim3(P.N2 * nt3, G), dim3(256), lds, st,
+                       static_cast<const cx<T> *>(slab), P.nslab, P.N2, P.N3, T3, nt3, nbands, ceil_div(nbands, G),
+                       P.row_to_slab, tw, occ, nb, b0, bbt, part, first);
+    return check_launch("density_x");
+}
+
 int local_inverse_planes(const Plan &P, int k0, int k1, int nb, int b0, int bbt, int fft_prec, int io_prec,
                          const void *psi, void *slab, hipStream_t st) {
     const BatchArgs ba{nb, P.pw_off[k0], b0, bbt};
@@ -719,11 +824,24 @@ int local_gradv_accumulate(const Plan &P, int fft_prec, const void *slab_x, cons
     }
 }
 
-int local_gradv_finish(const Plan &P, const double *part, int G, double *grad_v, hipStream_t st) {
+int local_density_accumulate(const Plan &P, int fft_prec, const void *slab, int nbands, const double *occ, int nb,
+                             int b0, int bbt, double *part, int G, int first, hipStream_t st) {
+    switch (P.N1) {
+#define APW_CASE(n)                                                                                                  \
+    case n:                                                                                                          \
+        return fft_prec == 0 ? launch_density<n, double>(P, slab, nbands, occ, nb, b0, bbt, part, G, first, st)     \
+                             : launch_density<n, float>(P, slab, nbands, occ, nb, b0, bbt, part, G, first, st);
+        APW_LENGTHS(APW_CASE)
+#undef APW_CASE
+        default:
+            return set_error(ABACUS_PW_EBAD_FFT_SIZE, "unsupported grid length");
+    }
+}
+
+int local_sum_parts(const Plan &P, const double *part, int G, double scale, double *out, hipStream_t st) {
     KernelTimer kt("gradv_reduce", st);
     const int64_t blocks = std::min<int64_t>(ceil_div64(P.N, 256), 8192);
-    hipLaunchKernelGGL(k_gradv_reduce, dim3((unsigned)blocks), dim3(256), 0, st, (int64_t)P.N, G, part, grad_v,
-                       1.0 / (double)P.N);
+    hipLaunchKernelGGL(k_gradv_reduce, dim3((unsigned)blocks), dim3(256), 0, st, (int64_t)P.N, G, part, out, scale);
     return check_launch("gradv_reduce");
 }
 

@@ -32,7 +32,11 @@ int local_inverse_planes(const Plan &P, int k0, int k1, int nb, int b0, int bbt,
 // psi (slab_x) and dY (slab_y); part is [G][N1][N2][N3]; first != 0 overwrites.
 int local_gradv_accumulate(const Plan &P, int fft_prec, const void *slab_x, const void *slab_y, int nbands,
                            double *part, int G, int first, hipStream_t st);
-// grad_v = (1/N) sum_g part[g]
-int local_gradv_finish(const Plan &P, const double *part, int G, double *grad_v, hipStream_t st);
+// part[g] (+)= sum over bands b = g (mod G) of w_b |psi_b(r)|^2 from the slab planes of psi;
+// virtual band b = kk * bbt + j of the batch has w_b = occ[kk * nb + b0 + j].
+int local_density_accumulate(const Plan &P, int fft_prec, const void *slab, int nbands, const double *occ, int nb,
+                             int b0, int bbt, double *part, int G, int first, hipStream_t st);
+// out = scale * sum_g part[g]   (fixed order)
+int local_sum_parts(const Plan &P, const double *part, int G, double scale, double *out, hipStream_t st);
 
 }  // namespace apw

@@ -125,3 +125,15 @@ def test_tuning_rejects_negative():
     assert code_name(B.lib().abacus_pw_set_tuning(0, 0, 0, 0, 3, 0)) == "EBAD_SHAPE"
     assert code_name(B.lib().abacus_pw_set_tuning(0, 0, 0, 0, 0, 3)) == "EBAD_SHAPE"
     assert B.lib().abacus_pw_set_tuning(0, 0, 0, 0, 0, 0) == 0
+
+
+def test_density_rejects_before_device_access(prob):
+    f = Fake(prob)
+    lib = B.lib()
+    assert code_name(lib.abacus_pw_density(C.byref(f.s), 0, 1, None, FAKE, FAKE, None)) == "ENULL_ARG"
+    assert code_name(lib.abacus_pw_density(C.byref(f.s), 0, 1, FAKE, None, FAKE, None)) == "ENULL_ARG"
+    assert code_name(lib.abacus_pw_density(C.byref(f.s), 0, 1, FAKE, FAKE, None, None)) == "ENULL_ARG"
+    assert code_name(lib.abacus_pw_density(C.byref(f.s), 0, 0, FAKE, FAKE, FAKE, None)) == "EBAD_SHAPE"
+    assert code_name(lib.abacus_pw_density(C.byref(f.s), 3, 1, FAKE, FAKE, FAKE, None)) == "EBAD_PRECISION"
+    f.miller[5] = f.miller[6]
+    assert code_name(lib.abacus_pw_density(C.byref(f.s), 0, 1, FAKE, FAKE, FAKE, None)) == "EBAD_SPHERE"
