@@ -14,7 +14,7 @@ recorded on the library's stream during the timed region), and the FP64 CPU
 oracle timed on this host.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-davidson] [--no-cg]
-                      [--no-batched] [--no-autotune] [--no-density]
+                      [--no-batched] [--no-autotune] [--no-density] [--no-backward]
 """
 from __future__ import annotations
 
@@ -50,6 +50,7 @@ def parse():
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-density", action="store_true")
+    ap.add_argument("--no-backward", action="store_true")
     ap.add_argument("--traffic-probe", action="store_true",
                     help="run a plain 256 MiB copy and a few H psi steps only (for counter collection)")
     return ap.parse_args()
@@ -320,6 +321,8 @@ def main():
 
     if not args.no_density:
         out["density"] = density_times(B, W, dev, prob, dp, x64, args.steps)
+    if not args.no_backward:
+        out["backward"] = backward_times(B, W, dev, max(5, args.steps // 4))
     if not args.no_davidson:
         out["davidson"] = davidson_times(B, W, dev)
     if not args.no_cg:
@@ -387,6 +390,55 @@ def density_times(B, W, dev, prob, dp, x, steps):
         by = bands * cb * S + 2 * 8 * 8 * N
         r["alg_bytes"] = by
         r["gbs"] = by / (r["avg_ms"] * 1e-3) / 1e9
+    return res
+
+
+def backward_times(B, W, dev, steps):
+    """Adjoint of H psi on the differentiation workload (C5: 96^3, k = G, X, M, R, 256 bands
+    each, 128 atoms x 4 projectors, complex128): grad_psi = H dY, grad_V from recomputed
+    grids, grad_D from two projections, FP64. k_gradv_x reads the psi and dY slab planes
+    (2 nb cb S per call) plus its partial grids (G = 8 of N doubles, read and written once
+    per band batch)."""
+    import torch
+    prob = W.make_problem("C5")
+    nb, nk = prob.nb, prob.nk
+    B.set_tuning()
+    dp = B.DeviceProblem(prob, device=dev, static=True)
+    x = torch.from_numpy(prob.psi).to(dev)
+    dy = torch.from_numpy(prob.dy).to(dev)
+    for _ in range(2):
+        B.apply_h_backward(dp, x, dy)
+    torch.cuda.synchronize()
+
+    def timed():
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        for _ in range(steps):
+            B.apply_h_backward(dp, x, dy)
+        b.record()
+        torch.cuda.synchronize()
+        return a.elapsed_time(b) / steps
+
+    B.profile_read()
+    B.profile_enable(True)
+    ms_ev = timed()
+    B.profile_enable(False)
+    kern = B.profile_read()
+    ms = timed()
+    cb, (n1, n2, n3) = 16, prob.fft
+    N = n1 * n2 * n3
+    m1 = prob.miller[:, 0]
+    S = (int(m1.max()) - int(m1.min()) + 1) * n2 * n3
+    rows = {name: {"launches_per_call": n / steps, "avg_ms": tot / n} for name, (n, tot) in kern.items()}
+    res = {"workload": "C5: cubic a=24 bohr, ecutwfc=35 Ry, 96^3, k = G, X, M, R (npw " +
+                       "/".join(str(int(n)) for n in prob.npw) + "), 256 bands each, 128 atoms x 4 projectors",
+           "ms_per_call": ms, "ms_per_call_with_kernel_events": ms_ev,
+           "band_adjoints_per_s": nk * nb / (ms * 1e-3), "kernels": rows}
+    if "gradv_x" in rows:
+        r = rows["gradv_x"]
+        bands = nk * nb / r["launches_per_call"]
+        r["alg_bytes"] = 2 * bands * cb * S + 2 * 8 * 8 * N
+        r["gbs"] = r["alg_bytes"] / (r["avg_ms"] * 1e-3) / 1e9
     return res
 
 

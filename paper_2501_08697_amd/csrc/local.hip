@@ -442,60 +442,97 @@ __global__ __launch_bounds__(256) void k_yz_fwd_c(const cx<T> *__restrict__ slab
 }
 
 // Adjoint of the local term with respect to V: for one (j2, j3 tile) and the
-// bands b = g, g + G, ... of the batch, inverse x transforms of the psi and dY
-// planes and acc(r) += Re(conj(gamma_b(r)) psi_b(r)); part[g] holds the running
-// sum (overwritten when first != 0). Bands are summed in a fixed order.
+// contiguous band range [g bpw, (g + 1) bpw) of the batch, inverse x transforms
+// of the psi and dY planes and acc(r) += Re(conj(gamma_b(r)) psi_b(r)); part[g]
+// holds the running sum (overwritten when first != 0). The transform is the
+// two-level one of k_density_x, applied to the sequence psi_bs, dY_bs,
+// psi_bs+1, ...: each source's phase-I values are fetched while the previous
+// source transforms, and psi's real-space values wait in registers for dY's.
+// Bands are summed in a fixed order.
 template <int N1, typename T>
 __global__ __launch_bounds__(256) void k_gradv_x(const cx<T> *__restrict__ slab_x, const cx<T> *__restrict__ slab_y,
-                                                 int nslab, int N2, int N3, int T3, int nt3, int nbands, int G,
+                                                 int nslab, int N2, int N3, int T3, int nt3, int nbands, int bpw,
                                                  const int *__restrict__ row_to_slab, const cx<T> *__restrict__ tw_g,
                                                  double *__restrict__ part, int first) {
-    constexpr int MAXV = (N1 * kMaxT3 + 255) / 256;
+    constexpr int A = LdsSplit<N1>::A, B = LdsSplit<N1>::B;
     extern __shared__ __align__(16) unsigned char smem[];
-    cx<T> *tile = reinterpret_cast<cx<T> *>(smem);
+    cx<T> *tile = reinterpret_cast<cx<T> *>(smem);       // [N1 slots][T3]
     cx<T> *tw = tile + N1 * T3;
+    int *r2s = reinterpret_cast<int *>(tw + N1);
     const int j2 = blockIdx.x / nt3, c0 = (blockIdx.x - j2 * nt3) * T3;
     const int w3 = min(T3, N3 - c0);
-    const int g = blockIdx.y;
-    const int tid = threadIdx.x, nthr = blockDim.x;
+    const int g = blockIdx.y, bs = g * bpw, be = min(nbands, bs + bpw);
+    const int tid = threadIdx.x;
     const int64_t plane = (int64_t)N2 * N3;
-    const int ntile = N1 * w3;
-    for (int i = tid; i < N1; i += nthr) tw[i] = tw_g[i];
-    double acc[MAXV];
-    cx<T> xr[MAXV];
-#pragma unroll
-    for (int q = 0; q < MAXV; ++q) acc[q] = 0.0;
-    for (int b = g; b < nbands; b += G) {
-        for (int src = 0; src < 2; ++src) {
-            const cx<T> *base = (src == 0 ? slab_x : slab_y) + (int64_t)b * nslab * plane + (int64_t)j2 * N3 + c0;
-            for (int i = tid; i < ntile; i += nthr) {
-                const int r = i / w3, c = i - r * w3;
-                const int s = row_to_slab[r];
-                tile[i] = s >= 0 ? base[s * plane + c] : czero<T>();
-            }
-            __syncthreads();
-            lds_fft<N1, +1, true>(tile, w3, [](int l) { return l; }, w3, tw);
-#pragma unroll
-            for (int q = 0; q < MAXV; ++q) {
-                const int i = tid + q * 256;
-                if (i < ntile) {
-                    if (src == 0) {
-                        xr[q] = tile[i];
-                    } else {
-                        const cx<T> y = tile[i];
-                        acc[q] += (double)y.re * (double)xr[q].re + (double)y.im * (double)xr[q].im;
-                    }
-                }
-            }
-            __syncthreads();
-        }
+    const int64_t bstride = (int64_t)nslab * plane;
+    for (int i = tid; i < N1; i += blockDim.x) {
+        tw[i] = tw_g[i];
+        r2s[i] = row_to_slab[i];
     }
+    __syncthreads();
+    const int c = w3 > 0 ? tid % w3 : 0;
+    const int ka = tid / w3, jb = tid / w3;
+    const bool has_ka = tid < w3 * A, has_jb = tid < w3 * B;
+    const int64_t col = (int64_t)j2 * N3 + c0 + c;
+    int64_t src[B];
 #pragma unroll
-    for (int q = 0; q < MAXV; ++q) {
-        const int i = tid + q * 256;
-        if (i < ntile) {
-            const int r = i / w3, c = i - r * w3;
-            double *o = part + (int64_t)g * N1 * plane + (int64_t)r * plane + (int64_t)j2 * N3 + c0 + c;
+    for (int kb = 0; kb < B; ++kb) {
+        const int sl = has_ka ? r2s[B * ka + kb] : -1;
+        src[kb] = sl >= 0 ? sl * plane : -1;
+    }
+    // source t: psi (t even) or dY (t odd) of band bs + t / 2
+    const int nt = 2 * max(0, be - bs);
+    auto source = [&](int t) { return ((t & 1) ? slab_y : slab_x) + (int64_t)(bs + (t >> 1)) * bstride + col; };
+    double acc[A];
+    cx<T> xr[A];
+#pragma unroll
+    for (int q = 0; q < A; ++q) {
+        acc[q] = 0.0;
+        xr[q] = czero<T>();
+    }
+    cx<T> pre[B];
+    {
+        const cx<T> *p0 = source(0);
+#pragma unroll
+        for (int kb = 0; kb < B; ++kb) pre[kb] = (has_ka && src[kb] >= 0 && nt > 0) ? p0[src[kb]] : czero<T>();
+    }
+    for (int t = 0; t < nt; ++t) {
+        if (has_ka) {
+            cx<T> z[B];
+#pragma unroll
+            for (int kb = 0; kb < B; ++kb) z[kb] = pre[kb];
+            if (t + 1 < nt) {
+                const cx<T> *pn = source(t + 1);
+#pragma unroll
+                for (int kb = 0; kb < B; ++kb)
+                    if (src[kb] >= 0) pre[kb] = pn[src[kb]];
+            }
+            RegDft<B, +1, T>::run(z);
+            tile[(B * ka) * T3 + c] = z[0];
+#pragma unroll
+            for (int q = 1; q < B; ++q) tile[(B * ka + q) * T3 + c] = cmul(z[q], tw[q * A + ka]);
+        }
+        __syncthreads();
+        if (has_jb) {
+            cx<T> a[A];
+#pragma unroll
+            for (int q = 0; q < A; ++q) a[q] = tile[(jb + B * q) * T3 + c];
+            RegDft<A, +1, T>::run(a);
+            if ((t & 1) == 0) {
+#pragma unroll
+                for (int q = 0; q < A; ++q) xr[q] = a[q];
+            } else {
+#pragma unroll
+                for (int q = 0; q < A; ++q)
+                    acc[q] += (double)a[q].re * (double)xr[q].re + (double)a[q].im * (double)xr[q].im;
+            }
+        }
+        __syncthreads();
+    }
+    if (has_jb) {
+#pragma unroll
+        for (int q = 0; q < A; ++q) {
+            double *o = part + (int64_t)g * N1 * plane + (int64_t)(jb + B * q) * plane + col;
             *o = first ? acc[q] : *o + acc[q];
         }
     }
@@ -768,8 +805,8 @@ size_t local_slab_bytes(const Plan &P, int fft_prec, int nbands) {
 template <int N1, typename T>
 static int launch_gradv(const Plan &P, const void *sx, const void *sy, int nbands, double *part, int G, int first,
                         hipStream_t st) {
-    const int T3 = std::min(xpass_tile(N1, P.N3), kMaxT3), nt3 = ceil_div(P.N3, T3);
-    const size_t lds = (size_t)(N1 * T3 + N1) * sizeof(cx<T>);
+    const int T3 = xpass_tile(N1, P.N3), nt3 = ceil_div(P.N3, T3);
+    const size_t lds = (size_t)(N1 * T3 + N1) * sizeof(cx<T>) + (size_t)N1 * sizeof(int);
     static bool once = false;
     if (!once) {
         APW_TRY(allow_lds(k_gradv_x<N1, T>, kLdsLimit));
@@ -778,8 +815,8 @@ static int launch_gradv(const Plan &P, const void *sx, const void *sy, int nband
     const cx<T> *tw = static_cast<const cx<T> *>(sizeof(T) == 8 ? P.tw64[0] : P.tw32[0]);
     KernelTimer kt("gradv_x", st);
     hipLaunchKernelGGL((k_gradv_x<N1, T>), dim3(P.N2 * nt3, G), dim3(256), lds, st, static_cast<const cx<T> *>(sx),
-                       static_cast<const cx<T> *>(sy), P.nslab, P.N2, P.N3, T3, nt3, nbands, G, P.row_to_slab, tw,
-                       part, first);
+                       static_cast<const cx<T> *>(sy), P.nslab, P.N2, P.N3, T3, nt3, nbands, ceil_div(nbands, G),
+                       P.row_to_slab, tw, part, first);
     return check_launch("gradv_x");
 }
 
