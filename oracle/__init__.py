@@ -1,4 +1,5 @@
-"""FP64 CPU oracle for the plane-wave H psi, its adjoint, the band density, and block Davidson.
+"""FP64 CPU oracle for the plane-wave H psi, its adjoint, the band density, the
+Chebyshev-filtered application, and block Davidson.
 
 TEST INFRASTRUCTURE ONLY: this package is used by ``tests/``, by the smoke
 check and by the benchmark's CPU-baseline leg. The GPU library never imports,
@@ -174,6 +175,44 @@ def density(prob, psi, occ, nb=None):
     rho = np.empty(tuple(prob.fft))
     lib().oracle_density(C.byref(b.s), nb, _ptr(x), _ptr(w), _ptr(rho))
     return rho
+
+
+# --------------------------------------------------------------------------
+# Chebyshev-filtered application (Sec. III.C: the stochastic orbitals are
+# filtered by f_H^{1/2}, expanded in Chebyshev polynomials of the scaled H).
+# --------------------------------------------------------------------------
+
+def chebyshev(prob, chi, coef, emin, emax, nb=None):
+    """out = sum_n coef[n] T_n(Hs) chi with Hs = (H - c) / h, c = (emax + emin) / 2,
+    h = (emax - emin) / 2, by the three-term recurrence T_{n+1} = 2 Hs T_n - T_{n-1}
+    (T_0 = 1, T_1 = Hs) on the packed block chi (per k a [nb][npw_k] block)."""
+    nb = prob.nb if nb is None else nb
+    coef = np.asarray(coef, dtype=np.float64)
+    c, h = 0.5 * (emax + emin), 0.5 * (emax - emin)
+    v0 = np.ascontiguousarray(chi, dtype=np.complex128)
+    out = coef[0] * v0
+    if coef.size == 1:
+        return out
+    v1 = (apply_h(prob, v0, nb=nb) - c * v0) / h
+    out = out + coef[1] * v1
+    for n in range(2, coef.size):
+        v2 = 2.0 * (apply_h(prob, v1, nb=nb) - c * v1) / h - v0
+        out = out + coef[n] * v2
+        v0, v1 = v1, v2
+    return out
+
+
+def fermi_sqrt_coefficients(order, emin, emax, mu, kt, power=0.5):
+    """Chebyshev interpolation coefficients (degree ``order``) of f(E)^power on [emin, emax],
+    f the Fermi-Dirac function 1 / (1 + exp((E - mu) / kt)) of Sec. III.C, via numpy's
+    Chebyshev interpolation at the Chebyshev points of the first kind."""
+    c, h = 0.5 * (emax + emin), 0.5 * (emax - emin)
+
+    def f(x):
+        e = c + h * x
+        return (0.5 * (1.0 - np.tanh(0.5 * (e - mu) / kt))) ** power
+
+    return np.polynomial.chebyshev.chebinterpolate(f, order)
 
 
 # --------------------------------------------------------------------------
