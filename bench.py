@@ -14,7 +14,7 @@ recorded on the library's stream during the timed region), and the FP64 CPU
 oracle timed on this host.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-davidson] [--no-cg]
-                      [--no-batched] [--no-autotune] [--no-density] [--no-backward]
+                      [--no-batched] [--no-autotune] [--no-density] [--no-backward] [--no-chebyshev]
 """
 from __future__ import annotations
 
@@ -51,6 +51,7 @@ def parse():
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-density", action="store_true")
     ap.add_argument("--no-backward", action="store_true")
+    ap.add_argument("--no-chebyshev", action="store_true")
     ap.add_argument("--traffic-probe", action="store_true",
                     help="run a plain 256 MiB copy and a few H psi steps only (for counter collection)")
     return ap.parse_args()
@@ -321,6 +322,8 @@ def main():
 
     if not args.no_density:
         out["density"] = density_times(B, W, dev, prob, dp, x64, args.steps)
+    if not args.no_chebyshev:
+        out["chebyshev"] = chebyshev_times(B, W, dev, prob, dp, ms64_clean)
     if not args.no_backward:
         out["backward"] = backward_times(B, W, dev, max(5, args.steps // 4))
     if not args.no_davidson:
@@ -390,6 +393,68 @@ def density_times(B, W, dev, prob, dp, x, steps):
         by = bands * cb * S + 2 * 8 * 8 * N
         r["alg_bytes"] = by
         r["gbs"] = by / (r["avg_ms"] * 1e-3) / 1e9
+    return res
+
+
+def chebyshev_times(B, W, dev, prob, dp, ms_apply):
+    """Chebyshev filter f_H^{1/2} (order 100, mu = 0.5 Ry, kT = 1 Ry) on 128 plane-wave
+    stochastic orbitals of the benchmark cell, FP64. Spectrum bounds by Weyl's inequality
+    (kinetic + local + nonlocal extremes), padded by 0.5 Ry.
+    k_cheb_step moves six vectors per element (H T_n, T_n, T_{n-1} and out read, T_{n+1}
+    and out written)."""
+    import torch
+    order, nb = 100, prob.nb
+    rec = W.reciprocal(np.asarray(prob.lattice, dtype=float))
+    kin = float(np.max(np.sum((prob.miller @ rec + np.asarray(prob.kpts)[0]) ** 2, axis=1)))
+    # Weyl: lambda_max(H) <= max |k+G|^2 + max(V, 0) + lambda_max(B D B^H), the last equal to
+    # lambda_max(G^1/2 D G^1/2) with G = B^H B the projector Gram matrix
+    beta = np.asarray(prob.beta).reshape(prob.nproj, -1)
+    gram = beta.conj() @ beta.T
+    w, u = np.linalg.eigh(gram)
+    gh = (u * np.sqrt(np.clip(w, 0, None))) @ u.conj().T
+    dfull = np.zeros((prob.nproj, prob.nproj))
+    o = 0
+    for a_ in range(prob.natom):
+        lo, hi = prob.proj_atom_offset[a_], prob.proj_atom_offset[a_ + 1]
+        dfull[lo:hi, lo:hi] = np.asarray(prob.dmat)[o: o + (hi - lo) ** 2].reshape(hi - lo, hi - lo)
+        o += (hi - lo) ** 2
+    nl_max = float(np.max(np.linalg.eigvalsh(gh @ dfull @ gh)))
+    emin = float(np.min(prob.vloc)) + min(0.0, float(np.min(np.linalg.eigvalsh(gh @ dfull @ gh)))) - 0.5
+    emax = kin + max(0.0, float(np.max(prob.vloc))) + nl_max + 0.5
+    coef = B.fermi_coefficients(order, emin, emax, 0.5, 1.0)
+    chi = torch.from_numpy(W.stochastic_orbitals(prob, nb, 0)).to(dev)
+    out = torch.empty_like(chi)
+    B.chebyshev(dp, chi, coef, emin, emax, out=out)
+    torch.cuda.synchronize()
+    steps = 3
+    B.profile_read()
+    B.profile_enable(True)
+    a, b2 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(steps):
+        B.chebyshev(dp, chi, coef, emin, emax, out=out)
+    b2.record()
+    torch.cuda.synchronize()
+    B.profile_enable(False)
+    kern = B.profile_read()
+    ms_ev = a.elapsed_time(b2) / steps
+    a, b2 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(steps):
+        B.chebyshev(dp, chi, coef, emin, emax, out=out)
+    b2.record()
+    torch.cuda.synchronize()
+    ms = a.elapsed_time(b2) / steps
+    n = nb * int(np.sum(prob.npw))
+    res = {"order": order, "orbitals": nb, "emin": emin, "emax": emax, "ms_per_call": ms,
+           "ms_per_call_with_kernel_events": ms_ev, "filtered_orbitals_per_s": nb / (ms * 1e-3),
+           "h_band_applies_per_s_inside": order * nb / (ms * 1e-3),
+           "overhead_vs_plain_apply": ms / (order * ms_apply)}
+    if "cheb_step" in kern:
+        cnt, tot = kern["cheb_step"]
+        avg = tot / cnt
+        res["cheb_step"] = {"launches_per_call": cnt / steps, "avg_ms": avg, "alg_bytes": 6 * 16 * n,
+                            "gbs": 6 * 16 * n / (avg * 1e-3) / 1e9}
     return res
 
 

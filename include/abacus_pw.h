@@ -220,6 +220,38 @@ int abacus_pw_apply_h_backward(const abacus_pw_problem *p, int precision, int nb
 int abacus_pw_density(const abacus_pw_problem *p, int precision, int nb, const void *psi, const double *occ,
                       double *rho, void *stream);
 
+/*
+ * Chebyshev-filtered application. Sec. III.C applies f_H^{1/2} (f_H the
+ * Fermi-Dirac operator) to stochastic orbitals through a Chebyshev expansion
+ * in H mapped onto [-1, 1]. This computes, for any coefficients,
+ *   out = sum_{n=0}^{order} coef[n] T_n(Hs) chi,  Hs = (H - c) / h,
+ *   c = (emax + emin) / 2, h = (emax - emin) / 2,
+ * with the three-term recurrence T_{n+1} = 2 Hs T_n - T_{n-1}: `order` applications
+ * of H to all nb bands. The expansion converges only when the spectrum of H lies
+ * in [emin, emax]; the library does not check this.
+ * chi, out  device, layout and type as in abacus_pw_apply_h (out must not alias chi);
+ *           out is overwritten.
+ * coef      host float64 [order + 1], read before the call returns.
+ * precision as in abacus_pw_apply_h; FP32 runs the recurrence in complex64, the other
+ *           modes in complex128 with H in that mode's precision.
+ * The library holds three work vectors of nb * sum(npw) complex values per plan.
+ * Asynchronous. Errors: ENULL_ARG, EBAD_SHAPE (order < 0, emax <= emin, aliasing),
+ * ENONFINITE (coefficients), and those of abacus_pw_apply_h.
+ */
+int abacus_pw_chebyshev(const abacus_pw_problem *p, int precision, int nb, const void *chi, void *out,
+                        const double *coef, int order, double emin, double emax, void *stream);
+
+/*
+ * Host routine: coefficients coef[0..order] of the degree-`order` Chebyshev
+ * interpolant on [emin, emax] of g(E) = f(E)^power, f(E) = 1 / (1 + exp((E - mu) / kt))
+ * the Fermi-Dirac function of Sec. III.C (power 1/2 gives the filter f_H^{1/2}),
+ * interpolated at the order + 1 Chebyshev points of the first kind. For use with
+ * abacus_pw_chebyshev and the same emin, emax. No device access.
+ * Errors: ENULL_ARG, EBAD_SHAPE (order < 0, emax <= emin, kt <= 0, power <= 0, non-finite).
+ */
+int abacus_pw_chebyshev_coefficients(int order, double emin, double emax, double mu, double kt, double power,
+                                     double *coef);
+
 /* Message for the last error on the calling thread (truncated to size). Returns len. */
 int abacus_pw_last_error(char *buf, int size);
 

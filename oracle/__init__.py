@@ -209,8 +209,9 @@ def fermi_sqrt_coefficients(order, emin, emax, mu, kt, power=0.5):
     c, h = 0.5 * (emax + emin), 0.5 * (emax - emin)
 
     def f(x):
-        e = c + h * x
-        return (0.5 * (1.0 - np.tanh(0.5 * (e - mu) / kt))) ** power
+        z = (c + h * x - mu) / kt
+        ez = np.exp(-np.abs(z))                    # the tail without cancellation
+        return np.where(z > 0, ez / (1.0 + ez), 1.0 / (1.0 + ez)) ** power
 
     return np.polynomial.chebyshev.chebinterpolate(f, order)
 

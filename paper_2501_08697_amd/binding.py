@@ -24,6 +24,7 @@ ERRORS = {
 }
 
 EXPORTS = ["abacus_pw_apply_h", "abacus_pw_davidson", "abacus_pw_cg", "abacus_pw_apply_h_backward", "abacus_pw_density",
+           "abacus_pw_chebyshev", "abacus_pw_chebyshev_coefficients",
            "abacus_pw_last_error",
            "abacus_pw_fft_supported", "abacus_pw_plan_reset", "abacus_pw_profile_enable",
            "abacus_pw_profile_read", "abacus_pw_set_tuning"]
@@ -60,6 +61,8 @@ def lib():
         L.abacus_pw_apply_h_backward.argtypes = [P, i, i, vp, vp, vp, vp, vp, vp]
         L.abacus_pw_davidson.argtypes = [P, i, i, vp, vp, d, i, i, vp, vp, vp]
         L.abacus_pw_density.argtypes = [P, i, i, vp, vp, vp, vp]
+        L.abacus_pw_chebyshev.argtypes = [P, i, i, vp, vp, vp, i, d, d, vp]
+        L.abacus_pw_chebyshev_coefficients.argtypes = [i, d, d, d, d, d, vp]
         L.abacus_pw_cg.argtypes = [P, i, vp, vp, d, i, vp, vp, vp]
         L.abacus_pw_last_error.argtypes = [C.c_char_p, i]
         L.abacus_pw_fft_supported.argtypes = [i]
@@ -184,6 +187,30 @@ def density(dp: DeviceProblem, psi, occ, precision: int = FP64, nb: int | None =
     check(lib().abacus_pw_density(C.byref(cp), int(precision), int(nb), psi.data_ptr(), w.data_ptr(), rho.data_ptr(),
                                   _stream(stream)))
     return rho
+
+
+def chebyshev(dp: DeviceProblem, chi, coef, emin, emax, precision: int = FP64, nb: int | None = None, stream=None,
+              out=None):
+    """sum_n coef[n] T_n((H - c)/h) chi, c and h the centre and half width of [emin, emax]."""
+    import torch
+    nb = dp.prob.nb if nb is None else nb
+    chi = chi.contiguous()
+    cf = np.ascontiguousarray(coef, dtype=np.float64).reshape(-1)
+    if cf.size < 1:
+        raise AbacusPwError(-2, "need at least one coefficient")
+    y = torch.empty_like(chi) if out is None else out
+    cp = dp.c()
+    check(lib().abacus_pw_chebyshev(C.byref(cp), int(precision), int(nb), chi.data_ptr(), y.data_ptr(),
+                                    cf.ctypes.data, int(cf.size - 1), float(emin), float(emax), _stream(stream)))
+    return y
+
+
+def fermi_coefficients(order: int, emin: float, emax: float, mu: float, kt: float, power: float = 0.5) -> np.ndarray:
+    """Chebyshev interpolation coefficients [order + 1] of the Fermi-Dirac function to `power`."""
+    cf = np.empty(int(order) + 1, dtype=np.float64)
+    check(lib().abacus_pw_chebyshev_coefficients(int(order), float(emin), float(emax), float(mu), float(kt),
+                                                 float(power), cf.ctypes.data))
+    return cf
 
 
 def davidson(dp: DeviceProblem, psi, tol=1e-8, max_iter=100, ndim=2, precision: int = FP64, nb: int | None = None,

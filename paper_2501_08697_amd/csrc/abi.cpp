@@ -1,4 +1,5 @@
 // C entry points, error messages and per-kernel timing.
+#include <cmath>
 #include <cstdio>
 #include <cstring>
 #include <map>
@@ -190,6 +191,37 @@ int abacus_pw_density(const abacus_pw_problem *p, int precision, int nb, const v
         Plan *P = nullptr;
         APW_TRY(get_plan(p, &P));
         return density_all(*p, *P, precision, nb, psi, occ, rho, static_cast<hipStream_t>(stream));
+    });
+}
+
+int abacus_pw_chebyshev(const abacus_pw_problem *p, int precision, int nb, const void *chi, void *out,
+                        const double *coef, int order, double emin, double emax, void *stream) {
+    return guarded([&]() -> int {
+        if (!chi || !out || !coef) return set_error(ABACUS_PW_ENULL_ARG, "chi, out and coef are required");
+        if (chi == out) return set_error(ABACUS_PW_EBAD_SHAPE, "out must not alias chi");
+        if (nb < 1 || order < 0) return set_error(ABACUS_PW_EBAD_SHAPE, "need nb >= 1 and order >= 0");
+        if (!std::isfinite(emin) || !std::isfinite(emax) || !(emax > emin))
+            return set_error(ABACUS_PW_EBAD_SHAPE, "need finite emin < emax");
+        for (int i = 0; i <= order; ++i)
+            if (!std::isfinite(coef[i])) return set_error(ABACUS_PW_ENONFINITE, "coefficient is not finite");
+        if (precision < 0 || precision > 3) return set_error(ABACUS_PW_EBAD_PRECISION, "unknown precision");
+        Plan *P = nullptr;
+        APW_TRY(get_plan(p, &P));
+        return chebyshev_all(*p, *P, precision, nb, chi, out, coef, order, emin, emax,
+                             static_cast<hipStream_t>(stream));
+    });
+}
+
+int abacus_pw_chebyshev_coefficients(int order, double emin, double emax, double mu, double kt, double power,
+                                     double *coef) {
+    return guarded([&]() -> int {
+        if (!coef) return set_error(ABACUS_PW_ENULL_ARG, "coef is required");
+        if (order < 0) return set_error(ABACUS_PW_EBAD_SHAPE, "need order >= 0");
+        if (!std::isfinite(emin) || !std::isfinite(emax) || !(emax > emin) || !std::isfinite(mu) ||
+            !(kt > 0.0) || !std::isfinite(kt) || !(power > 0.0) || !std::isfinite(power))
+            return set_error(ABACUS_PW_EBAD_SHAPE, "need finite emin < emax, mu, kt > 0 and power > 0");
+        fermi_coefficients(order, emin, emax, mu, kt, power, coef);
+        return ABACUS_PW_OK;
     });
 }
 

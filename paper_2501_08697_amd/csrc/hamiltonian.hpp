@@ -28,6 +28,13 @@ int apply_h_backward_all(const abacus_pw_problem &p, Plan &P, int prec, int nb, 
 int density_all(const abacus_pw_problem &p, Plan &P, int prec, int nb, const void *psi, const double *occ,
                 double *rho, hipStream_t st);
 
+// out = sum_{n<=order} coef[n] T_n((H - c)/h) chi, c and h the centre and half width of
+// [emin, emax]; coef is host memory, read during the call.
+int chebyshev_all(const abacus_pw_problem &p, Plan &P, int prec, int nb, const void *chi, void *out,
+                  const double *coef, int order, double emin, double emax, hipStream_t st);
+// Chebyshev interpolation coefficients [order + 1] of the Fermi-Dirac function to a power.
+void fermi_coefficients(int order, double emin, double emax, double mu, double kt, double power, double *coef);
+
 // Band-by-band preconditioned CG (abacus_pw_cg).
 int cg_all(const abacus_pw_problem &p, Plan &P, int nb, void *psi, double *eig, double tol, int max_iter, int *iters,
            double *resid, hipStream_t st);

@@ -99,6 +99,7 @@ struct Plan {
     DeviceBuffer projq2;
     DeviceBuffer gradv_part;  // band-group partial sums of grad V
     DeviceBuffer tmp_io;      // precision staging
+    DeviceBuffer cheb[3];     // Chebyshev recurrence: two polynomial terms and H applied to one
 };
 
 // Global tuning knobs (abacus_pw_set_tuning); 0 selects the library default.

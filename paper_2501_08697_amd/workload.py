@@ -322,3 +322,14 @@ def band_weights(prob, seed: int = 0) -> np.ndarray:
     rng = np.random.default_rng(1000 + seed)
     nk = len(prob.npw)
     return rng.uniform(0.0, 2.0, size=(nk, prob.nb)) / nk
+
+
+def stochastic_orbitals(prob, nchi: int, seed: int = 0) -> np.ndarray:
+    """Plane-wave stochastic orbitals of Sec. III.C: per k-point and orbital a,
+    chi_a(G) = exp(2 pi i theta) / sqrt(nchi) with theta ~ U(0, 1) drawn
+    independently for every (k, a, G) from the stream of seed 2000 + seed.
+    Packed like psi: per k a [nchi][npw_k] block, complex128."""
+    rng = np.random.default_rng(2000 + seed)
+    blocks = [np.exp(2j * np.pi * rng.uniform(0.0, 1.0, size=(nchi, int(n)))) / np.sqrt(nchi)
+              for n in prob.npw]
+    return np.concatenate([b.reshape(-1) for b in blocks]).astype(np.complex128)

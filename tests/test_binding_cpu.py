@@ -137,3 +137,44 @@ def test_density_rejects_before_device_access(prob):
     assert code_name(lib.abacus_pw_density(C.byref(f.s), 3, 1, FAKE, FAKE, FAKE, None)) == "EBAD_PRECISION"
     f.miller[5] = f.miller[6]
     assert code_name(lib.abacus_pw_density(C.byref(f.s), 0, 1, FAKE, FAKE, FAKE, None)) == "EBAD_SPHERE"
+
+
+def test_chebyshev_rejects_before_device_access(prob):
+    f = Fake(prob)
+    lib = B.lib()
+    cf = np.array([1.0, 0.5, 0.25])
+    p = cf.ctypes.data
+
+    def call(chi=FAKE, out=FAKE + 64, coef=p, order=2, emin=-1.0, emax=1.0, prec=0, nb=1):
+        return code_name(lib.abacus_pw_chebyshev(C.byref(f.s), prec, nb, chi, out, coef, order, emin, emax, None))
+
+    assert call(chi=None) == "ENULL_ARG"
+    assert call(coef=None) == "ENULL_ARG"
+    assert call(out=FAKE) == "EBAD_SHAPE"
+    assert call(order=-1) == "EBAD_SHAPE"
+    assert call(emin=1.0) == "EBAD_SHAPE"
+    assert call(emax=float("nan")) == "EBAD_SHAPE"
+    assert call(prec=9) == "EBAD_PRECISION"
+    bad = np.array([1.0, float("inf")])
+    assert code_name(lib.abacus_pw_chebyshev(C.byref(f.s), 0, 1, FAKE, FAKE + 64, bad.ctypes.data, 1, -1.0, 1.0,
+                                             None)) == "ENONFINITE"
+
+
+def test_fermi_coefficients_match_oracle_interpolation():
+    """The library's host routine against numpy's Chebyshev interpolation (the oracle's route)."""
+    import oracle
+    for order, kt, power in ((0, 1.0, 0.5), (1, 0.7, 0.5), (60, 2.0, 0.5), (300, 0.5, 1.0), (1200, 0.2, 0.5)):
+        ref = oracle.fermi_sqrt_coefficients(order, -2.0, 35.0, 1.3, kt, power)
+        got = B.fermi_coefficients(order, -2.0, 35.0, 1.3, kt, power)
+        assert got.shape == ref.shape
+        assert np.max(np.abs(got - ref)) < 1e-13, (order, np.max(np.abs(got - ref)))
+
+
+def test_fermi_coefficients_reject_bad_arguments():
+    out = np.empty(4)
+    lib = B.lib()
+    assert code_name(lib.abacus_pw_chebyshev_coefficients(3, 0.0, 1.0, 0.0, 1.0, 0.5, None)) == "ENULL_ARG"
+    assert code_name(lib.abacus_pw_chebyshev_coefficients(-1, 0.0, 1.0, 0.0, 1.0, 0.5, out.ctypes.data)) == "EBAD_SHAPE"
+    assert code_name(lib.abacus_pw_chebyshev_coefficients(3, 1.0, 1.0, 0.0, 1.0, 0.5, out.ctypes.data)) == "EBAD_SHAPE"
+    assert code_name(lib.abacus_pw_chebyshev_coefficients(3, 0.0, 1.0, 0.0, 0.0, 0.5, out.ctypes.data)) == "EBAD_SHAPE"
+    assert code_name(lib.abacus_pw_chebyshev_coefficients(3, 0.0, 1.0, 0.0, 1.0, -1.0, out.ctypes.data)) == "EBAD_SHAPE"
