@@ -1,5 +1,5 @@
 """FP64 CPU oracle for the plane-wave H psi, its adjoint, the band density, the
-Chebyshev-filtered application, and block Davidson.
+nonlocal force, the Chebyshev-filtered application, and block Davidson.
 
 TEST INFRASTRUCTURE ONLY: this package is used by ``tests/``, by the smoke
 check and by the benchmark's CPU-baseline leg. The GPU library never imports,
@@ -175,6 +175,85 @@ def density(prob, psi, occ, nb=None):
     rho = np.empty(tuple(prob.fft))
     lib().oracle_density(C.byref(b.s), nb, _ptr(x), _ptr(w), _ptr(rho))
     return rho
+
+
+# --------------------------------------------------------------------------
+# Nonlocal energy and force (Sec. III.A: the Kleinman-Bylander energy and its
+# derivative with respect to the atomic positions).
+# --------------------------------------------------------------------------
+
+def _kplusg(prob, k):
+    """Cartesian k + G of the sphere points of k-point k, [npw][3] (bohr^-1)."""
+    a = np.asarray(prob.lattice, dtype=np.float64).reshape(3, 3)
+    recip = 2.0 * np.pi * np.linalg.inv(a).T           # rows b_i with a_i . b_j = 2 pi delta_ij
+    off = int(np.sum(prob.npw[:k]))
+    m = np.asarray(prob.miller).reshape(-1, 3)[off: off + int(prob.npw[k])].astype(np.float64)
+    return m @ recip + np.asarray(prob.kpts, dtype=np.float64).reshape(-1, 3)[k]
+
+
+def _beta_k(prob, k):
+    off = int(np.sum(prob.npw[:k]))
+    return np.asarray(prob.beta).reshape(-1)[prob.nproj * off: prob.nproj * (off + int(prob.npw[k]))].reshape(
+        prob.nproj, int(prob.npw[k]))
+
+
+def _d_blocks(prob):
+    out, o = [], 0
+    d = np.asarray(prob.dmat, dtype=np.float64).reshape(-1)
+    for a in range(prob.natom):
+        lo, hi = int(prob.proj_atom_offset[a]), int(prob.proj_atom_offset[a + 1])
+        out.append((lo, hi, d[o: o + (hi - lo) ** 2].reshape(hi - lo, hi - lo)))
+        o += (hi - lo) ** 2
+    return out
+
+
+def nonlocal_energy(prob, psi, occ, nb=None, shift=None):
+    """E_NL = sum_k sum_n occ[k][n] sum_a sum_{i,j in a} conj(P_in) D^a_ij P_jn, P = B^H psi.
+    shift ([natom][3] bohr) moves the atoms: the projectors carry exp(-i (k+G).tau_a), so
+    moving atom a by delta multiplies its projectors by exp(-i (k+G).delta)."""
+    nb = prob.nb if nb is None else nb
+    occ = np.asarray(occ, dtype=np.float64).reshape(len(prob.npw), nb)
+    x = np.asarray(psi)
+    e = 0.0
+    off = 0
+    for k in range(len(prob.npw)):
+        npw = int(prob.npw[k])
+        bk = _beta_k(prob, k).copy()
+        if shift is not None:
+            kg = _kplusg(prob, k)
+            for a, (lo, hi, _) in enumerate(_d_blocks(prob)):
+                bk[lo:hi] *= np.exp(-1j * (kg @ np.asarray(shift[a], dtype=np.float64)))[None, :]
+        xk = x[nb * off: nb * (off + npw)].reshape(nb, npw)
+        P = bk.conj() @ xk.T                                  # [nproj][nb]
+        for lo, hi, d in _d_blocks(prob):
+            q = P[lo:hi]
+            e += float(np.real(np.sum(occ[k][None, :] * (q.conj() * (d @ q)))))
+        off += npw
+    return e
+
+
+def force_nl(prob, psi, occ, nb=None):
+    """F[a][alpha] = -dE_NL/dtau_{a,alpha} = -2 sum_k sum_n occ[k][n] sum_{i,j in a}
+    D^a_ij Im(conj(P^alpha_in) P_jn), with P = B^H psi and P^alpha = B^H ((k+G)_alpha psi)
+    (d beta / d tau_alpha = -i (k+G)_alpha beta). Ry / bohr."""
+    nb = prob.nb if nb is None else nb
+    occ = np.asarray(occ, dtype=np.float64).reshape(len(prob.npw), nb)
+    x = np.asarray(psi)
+    f = np.zeros((prob.natom, 3))
+    off = 0
+    for k in range(len(prob.npw)):
+        npw = int(prob.npw[k])
+        bk = _beta_k(prob, k)
+        kg = _kplusg(prob, k)
+        xk = x[nb * off: nb * (off + npw)].reshape(nb, npw)
+        P = bk.conj() @ xk.T
+        for al in range(3):
+            Pa = bk.conj() @ (xk * kg[None, :, al]).T
+            for a, (lo, hi, d) in enumerate(_d_blocks(prob)):
+                z = Pa[lo:hi].conj() * (d @ P[lo:hi])            # [i][n]: conj(P^a_in) sum_j D_ij P_jn
+                f[a, al] -= 2.0 * float(np.sum(occ[k][None, :] * np.imag(z)))
+        off += npw
+    return f
 
 
 # --------------------------------------------------------------------------
