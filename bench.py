@@ -15,6 +15,7 @@ oracle timed on this host.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-davidson] [--no-cg]
                       [--no-batched] [--no-autotune] [--no-density] [--no-backward] [--no-chebyshev]
+                      [--no-force]
 """
 from __future__ import annotations
 
@@ -52,6 +53,7 @@ def parse():
     ap.add_argument("--no-density", action="store_true")
     ap.add_argument("--no-backward", action="store_true")
     ap.add_argument("--no-chebyshev", action="store_true")
+    ap.add_argument("--no-force", action="store_true")
     ap.add_argument("--traffic-probe", action="store_true",
                     help="run a plain 256 MiB copy and a few H psi steps only (for counter collection)")
     return ap.parse_args()
@@ -322,6 +324,8 @@ def main():
 
     if not args.no_density:
         out["density"] = density_times(B, W, dev, prob, dp, x64, args.steps)
+    if not args.no_force:
+        out["force_nl"] = force_times(B, W, dev, prob, dp, x64, args.steps)
     if not args.no_chebyshev:
         out["chebyshev"] = chebyshev_times(B, W, dev, prob, dp, ms64_clean)
     if not args.no_backward:
@@ -393,6 +397,36 @@ def density_times(B, W, dev, prob, dp, x, steps):
         by = bands * cb * S + 2 * 8 * 8 * N
         r["alg_bytes"] = by
         r["gbs"] = by / (r["avg_ms"] * 1e-3) / 1e9
+    return res
+
+
+def force_times(B, W, dev, prob, dp, x, steps):
+    """Nonlocal force on the 64 atoms of the benchmark cell from its 128 bands, FP64: one
+    stacking pass over beta, one GEMM [B; (k+G)_x B; (k+G)_y B; (k+G)_z B]^H psi
+    (8 (4 nproj) nb npw flops), one reduction per atom."""
+    import torch
+    occ = torch.from_numpy(W.band_weights(prob, 0)).to(dev)
+    for _ in range(2):
+        B.force_nl(dp, x, occ)
+    torch.cuda.synchronize()
+    B.profile_read()
+    B.profile_enable(True)
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(steps):
+        B.force_nl(dp, x, occ)
+    b.record()
+    torch.cuda.synchronize()
+    B.profile_enable(False)
+    kern = B.profile_read()
+    ms = a.elapsed_time(b) / steps
+    npw = int(prob.npw[0])
+    flops = 8.0 * 4 * prob.nproj * prob.nb * npw
+    rows = {name: {"launches_per_call": n / steps, "avg_ms": tot / n} for name, (n, tot) in kern.items()}
+    res = {"ms_per_call_with_kernel_events": ms, "gemm_flops": flops, "kernels": rows}
+    if "gemm_cn" in rows:
+        res["gemm_tflops"] = flops / (rows["gemm_cn"]["avg_ms"] * 1e-3) / 1e12
+        res["gemm_frac_fp64_peak"] = res["gemm_tflops"] / FP64_PEAK_TFLOPS
     return res
 
 

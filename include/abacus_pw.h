@@ -221,6 +221,24 @@ int abacus_pw_density(const abacus_pw_problem *p, int precision, int nb, const v
                       double *rho, void *stream);
 
 /*
+ * Nonlocal (Kleinman-Bylander) force on every atom, the derivative of the
+ * projector energy with respect to the atomic positions (Sec. III.A). With the
+ * projectors carrying the structure factor exp(-i (k+G).tau_a):
+ *   E_NL = sum_k sum_n occ[k][n] sum_a P_a^H D_a P_a,  P = B^H psi,
+ *   F[a][alpha] = -dE_NL/dtau_{a,alpha}
+ *               = -2 sum_k sum_n occ[k][n] sum_{i,j in a} D_ij Im(conj(P^alpha_in) P_jn),
+ *   P^alpha = B^H ((k+G)_alpha psi),  (k+G) Cartesian in bohr^-1.
+ * psi       device complex128 packed [k][nb][npw_k] (FP64 only).
+ * occ       device float64 [nk][nb]: weight of each band (k weight x occupation x spin).
+ * force     device float64 [natom][3], Ry / bohr, overwritten.
+ * At most 16 projectors per atom. Sums over bands and k run in a fixed order.
+ * Asynchronous. Errors: ENULL_ARG, EBAD_SHAPE, EBAD_PRECISION (not FP64), and those
+ * of abacus_pw_apply_h.
+ */
+int abacus_pw_force_nl(const abacus_pw_problem *p, int precision, int nb, const void *psi, const double *occ,
+                       double *force, void *stream);
+
+/*
  * Chebyshev-filtered application. Sec. III.C applies f_H^{1/2} (f_H the
  * Fermi-Dirac operator) to stochastic orbitals through a Chebyshev expansion
  * in H mapped onto [-1, 1]. This computes, for any coefficients,

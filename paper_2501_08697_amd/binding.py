@@ -24,7 +24,7 @@ ERRORS = {
 }
 
 EXPORTS = ["abacus_pw_apply_h", "abacus_pw_davidson", "abacus_pw_cg", "abacus_pw_apply_h_backward", "abacus_pw_density",
-           "abacus_pw_chebyshev", "abacus_pw_chebyshev_coefficients",
+           "abacus_pw_chebyshev", "abacus_pw_chebyshev_coefficients", "abacus_pw_force_nl",
            "abacus_pw_last_error",
            "abacus_pw_fft_supported", "abacus_pw_plan_reset", "abacus_pw_profile_enable",
            "abacus_pw_profile_read", "abacus_pw_set_tuning"]
@@ -62,6 +62,7 @@ def lib():
         L.abacus_pw_davidson.argtypes = [P, i, i, vp, vp, d, i, i, vp, vp, vp]
         L.abacus_pw_density.argtypes = [P, i, i, vp, vp, vp, vp]
         L.abacus_pw_chebyshev.argtypes = [P, i, i, vp, vp, vp, i, d, d, vp]
+        L.abacus_pw_force_nl.argtypes = [P, i, i, vp, vp, vp, vp]
         L.abacus_pw_chebyshev_coefficients.argtypes = [i, d, d, d, d, d, vp]
         L.abacus_pw_cg.argtypes = [P, i, vp, vp, d, i, vp, vp, vp]
         L.abacus_pw_last_error.argtypes = [C.c_char_p, i]
@@ -187,6 +188,21 @@ def density(dp: DeviceProblem, psi, occ, precision: int = FP64, nb: int | None =
     check(lib().abacus_pw_density(C.byref(cp), int(precision), int(nb), psi.data_ptr(), w.data_ptr(), rho.data_ptr(),
                                   _stream(stream)))
     return rho
+
+
+def force_nl(dp: DeviceProblem, psi, occ, nb: int | None = None, stream=None):
+    """Nonlocal force [natom][3] (Ry/bohr, device float64) for band weights occ [nk][nb]."""
+    import torch
+    nb = dp.prob.nb if nb is None else nb
+    psi = psi.contiguous()
+    w = torch.as_tensor(occ, dtype=torch.float64).to(psi.device).contiguous()
+    if w.numel() != dp.nk * nb:
+        raise AbacusPwError(-2, f"occ must hold nk * nb = {dp.nk * nb} weights, got {w.numel()}")
+    f = torch.empty((dp.natom, 3), dtype=torch.float64, device=psi.device)
+    cp = dp.c()
+    check(lib().abacus_pw_force_nl(C.byref(cp), FP64, int(nb), psi.data_ptr(), w.data_ptr(), f.data_ptr(),
+                                   _stream(stream)))
+    return f
 
 
 def chebyshev(dp: DeviceProblem, chi, coef, emin, emax, precision: int = FP64, nb: int | None = None, stream=None,

@@ -194,6 +194,18 @@ int abacus_pw_density(const abacus_pw_problem *p, int precision, int nb, const v
     });
 }
 
+int abacus_pw_force_nl(const abacus_pw_problem *p, int precision, int nb, const void *psi, const double *occ,
+                       double *force, void *stream) {
+    return guarded([&]() -> int {
+        if (!psi || !occ || !force) return set_error(ABACUS_PW_ENULL_ARG, "psi, occ and force are required");
+        if (nb < 1) return set_error(ABACUS_PW_EBAD_SHAPE, "nb must be >= 1");
+        if (precision != ABACUS_PW_FP64) return set_error(ABACUS_PW_EBAD_PRECISION, "the force runs in FP64");
+        Plan *P = nullptr;
+        APW_TRY(get_plan(p, &P));
+        return force_nl_all(*p, *P, nb, psi, occ, force, static_cast<hipStream_t>(stream));
+    });
+}
+
 int abacus_pw_chebyshev(const abacus_pw_problem *p, int precision, int nb, const void *chi, void *out,
                         const double *coef, int order, double emin, double emax, void *stream) {
     return guarded([&]() -> int {

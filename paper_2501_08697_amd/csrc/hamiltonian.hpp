@@ -30,6 +30,10 @@ int density_all(const abacus_pw_problem &p, Plan &P, int prec, int nb, const voi
 
 // out = sum_{n<=order} coef[n] T_n((H - c)/h) chi, c and h the centre and half width of
 // [emin, emax]; coef is host memory, read during the call.
+// Nonlocal force F[natom][3] (Ry/bohr) = -dE_NL/dtau with E_NL = sum_{k,n} occ[k][n] <psi|V_NL|psi>;
+// occ device [nk][nb]; force device, overwritten. FP64.
+int force_nl_all(const abacus_pw_problem &p, Plan &P, int nb, const void *psi, const double *occ, double *force,
+                 hipStream_t st);
 int chebyshev_all(const abacus_pw_problem &p, Plan &P, int prec, int nb, const void *chi, void *out,
                   const double *coef, int order, double emin, double emax, hipStream_t st);
 // Chebyshev interpolation coefficients [order + 1] of the Fermi-Dirac function to a power.

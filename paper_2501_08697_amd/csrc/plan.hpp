@@ -100,6 +100,9 @@ struct Plan {
     DeviceBuffer gradv_part;  // band-group partial sums of grad V
     DeviceBuffer tmp_io;      // precision staging
     DeviceBuffer cheb[3];     // Chebyshev recurrence: two polynomial terms and H applied to one
+    DeviceBuffer force_tab;   // nonlocal force: (k+G) [npw_total][3] float64, then atom offsets [natom+1]
+    bool force_tab_ready = false;
+    DeviceBuffer force_stack; // [4 nproj][npw_k] complex128: beta, (k+G)_x beta, (k+G)_y beta, (k+G)_z beta
 };
 
 // Global tuning knobs (abacus_pw_set_tuning); 0 selects the library default.

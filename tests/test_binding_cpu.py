@@ -178,3 +178,13 @@ def test_fermi_coefficients_reject_bad_arguments():
     assert code_name(lib.abacus_pw_chebyshev_coefficients(3, 1.0, 1.0, 0.0, 1.0, 0.5, out.ctypes.data)) == "EBAD_SHAPE"
     assert code_name(lib.abacus_pw_chebyshev_coefficients(3, 0.0, 1.0, 0.0, 0.0, 0.5, out.ctypes.data)) == "EBAD_SHAPE"
     assert code_name(lib.abacus_pw_chebyshev_coefficients(3, 0.0, 1.0, 0.0, 1.0, -1.0, out.ctypes.data)) == "EBAD_SHAPE"
+
+
+def test_force_rejects_before_device_access(prob):
+    f = Fake(prob)
+    lib = B.lib()
+    assert code_name(lib.abacus_pw_force_nl(C.byref(f.s), 0, 1, None, FAKE, FAKE, None)) == "ENULL_ARG"
+    assert code_name(lib.abacus_pw_force_nl(C.byref(f.s), 0, 1, FAKE, None, FAKE, None)) == "ENULL_ARG"
+    assert code_name(lib.abacus_pw_force_nl(C.byref(f.s), 0, 1, FAKE, FAKE, None, None)) == "ENULL_ARG"
+    assert code_name(lib.abacus_pw_force_nl(C.byref(f.s), 0, 0, FAKE, FAKE, FAKE, None)) == "EBAD_SHAPE"
+    assert code_name(lib.abacus_pw_force_nl(C.byref(f.s), 1, 1, FAKE, FAKE, FAKE, None)) == "EBAD_PRECISION"
