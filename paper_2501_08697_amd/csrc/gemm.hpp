@@ -41,16 +41,23 @@ int reduce_dapply_f32(int M, int N, int nsplit, const void *part, const double *
                       const int *bdoff, void *Q, hipStream_t st);
 
 // ---- BF16 operands, FP32 accumulation (gemm_bf16.hip) ----
-// out[i] = complex128 in[i] rounded to a packed bf16 pair (re low, im high).
-int pack_bf16(int64_t n, const void *in, void *out, hipStream_t st);
+// Leading dimension of packed bf16 rows of K values: K rounded up to a multiple of 32.
+inline int bf16_ld(int K) { return (K + 31) / 32 * 32; }
+// out[r][c] = in[r][c] (complex128 when in_is_f64, else complex64) rounded to a packed bf16 pair
+// (re low, im high) for c < K, 0 for K <= c < ldo.
+int pack_bf16_rows(int rows, int K, const void *in, int in_is_f64, int64_t ldi, void *out, int64_t ldo,
+                   hipStream_t st);
 size_t gemm_cn_bf16_part_bytes(int M, int N, int K, int chunk_hint);
-// Q[j][i] = sum_t D_blk(i) P[j][.], P[j][i] = <beta_i|psi_j> with bf16 operands (Bpk packed bf16 beta,
-// psi complex128 when psi_is_f64 else complex64); Q complex64 [N][M].
-int proj_dapply_bf16(int M, int N, int K, const void *Bpk, int64_t ldb, const void *psi, int psi_is_f64, int64_t ldp,
+// Q[j][i] = sum_t D_blk(i) P[j][.], P[j][i] = <beta_i|psi_j> with bf16 operands: Bpk packed bf16 beta
+// [M][ldb], psi_pk packed bf16 psi [N][ldp], both with zero-padded rows (ldb, ldp = bf16_ld(K)).
+int proj_dapply_bf16(int M, int N, int K, const void *Bpk, int64_t ldb, const void *psi_pk, int64_t ldp,
                      const double *dmat, const int *blo, const int *bn, const int *bdoff, void *Q, void *part,
                      int chunk_hint, hipStream_t st);
-// C[j][g] += sum_i A[j][i] B[i][g], A complex64, B packed bf16, C complex128.
-int gemm_nn_bf16_into_f64(int M, int G, int K, const void *A, int64_t lda, const void *Bpk, int64_t ldb, void *C,
+// out[g][i] = in[i][g] (complex128 [rows][ldi], g < cols) as packed bf16, zero for rows <= i < ldo.
+int pack_bf16_transpose(int rows, int cols, const void *in, int64_t ldi, void *out, int64_t ldo, hipStream_t st);
+// C[j][g] += sum_i A[j][i] B[i][g] for j < N, g < G, i < K: Apk packed bf16 A [N][lda], BTpk packed bf16
+// transposed B [G][ldbt], lda and ldbt = bf16_ld(K) with zero padding; C complex128 [N][ldc].
+int gemm_nn_bf16_into_f64(int N, int G, int K, const void *Apk, int64_t lda, const void *BTpk, int64_t ldbt, void *C,
                           int64_t ldc, hipStream_t st);
 
 }  // namespace apw

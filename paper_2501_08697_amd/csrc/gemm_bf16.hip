@@ -3,11 +3,11 @@
 // MIXED_BF16 mode:
 //
 //   CN  part[s][j][i] = sum_{k in split s} conj(A[i][k]) B[j][k]
-//       A: beta as packed complex bf16 (re in the low half-word), B: psi as
-//       complex128 or complex64, rounded to bf16 while it is staged in LDS.
-//   NN  C[j][g] += sum_i A[j][i] B[i][g]
-//       A: Q = D P as complex64 (rounded to bf16 in LDS), B: beta packed bf16,
-//       C: complex128 H psi.
+//       A: beta, B: psi, both as packed complex bf16 (re in the low half-word)
+//       rows padded with zeros to a multiple of 32.
+//   NN  C[j][g] += sum_i Q[j][i] beta[i][g]
+//       Q = D P and the transposed beta [g][i], both packed bf16 with the
+//       projector index padded to a multiple of 32; C: complex128 H psi.
 //
 // The instruction takes eight consecutive k of A and of B per lane (A[i][k]
 // at lane i + 16 (k / 8), B[k][j] at lane j + 16 (k / 8)) and returns D[i][j]
@@ -32,210 +32,232 @@ template <typename T> __device__ __forceinline__ uint32_t pack_c(cx<T> v) {
     return pack_bf16(static_cast<float>(v.re), static_cast<float>(v.im));
 }
 
-// Split 8 packed complex bf16 values into real and imaginary bf16 vectors.
-__device__ __forceinline__ void unpack8(const uint32_t *p, bf8 &re, bf8 &im, bool neg_im) {
+__device__ __forceinline__ f4 mma(bf8 a, bf8 b, f4 c) { return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0); }
+
+
+// ---------------------------------------------------------------------------
+// CN with 128 x 128 work-group tiles. Both operands are packed bf16 rows whose
+// leading dimension is a multiple of 32 and whose padding is zero, so every
+// stage of 32 k is a set of aligned 16-byte loads with no bounds on k. The
+// loaders split each packed pair into planar real and imaginary bf16 rows in
+// LDS (v_perm), so a lane's MFMA fragment (eight consecutive k of one row) is
+// one 16-byte LDS read. Each wave owns a 64 x 64 quarter: 4 x 4 tiles of
+// 16 x 16, four MFMAs per tile per stage (conj(a) b). The next stage's global
+// values are fetched into registers while the current stage computes.
+// ---------------------------------------------------------------------------
+constexpr int T2 = 128;           // work-group tile (rows of A and of B)
+constexpr int BK2 = 32;           // k per stage
+constexpr int P2 = 20;            // LDS row pitch in 32-bit words (16 bf16 pairs + 4 pad; 80 bytes)
+
+typedef unsigned int u4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ bf8 as_bf8(u4 v) { return __builtin_bit_cast(bf8, v); }
+
+// 16 packed pairs (re low, im high) -> 8 words of real pairs and 8 words of imaginary pairs
+__device__ __forceinline__ void split16(const u4 g[4], u4 re[2], u4 im[2]) {
 #pragma unroll
-    for (int t = 0; t < 8; ++t) {
-        const unsigned short r = (unsigned short)(p[t] & 0xFFFFu);
-        unsigned short i = (unsigned short)(p[t] >> 16);
-        if (neg_im) i ^= 0x8000u;
-        re[t] = __builtin_bit_cast(__bf16, r);
-        im[t] = __builtin_bit_cast(__bf16, i);
+    for (int h = 0; h < 2; ++h) {
+        const u4 a = g[2 * h], b = g[2 * h + 1];
+        re[h] = u4{__builtin_amdgcn_perm(a.y, a.x, 0x05040100u), __builtin_amdgcn_perm(a.w, a.z, 0x05040100u),
+                   __builtin_amdgcn_perm(b.y, b.x, 0x05040100u), __builtin_amdgcn_perm(b.w, b.z, 0x05040100u)};
+        im[h] = u4{__builtin_amdgcn_perm(a.y, a.x, 0x07060302u), __builtin_amdgcn_perm(a.w, a.z, 0x07060302u),
+                   __builtin_amdgcn_perm(b.y, b.x, 0x07060302u), __builtin_amdgcn_perm(b.w, b.z, 0x07060302u)};
     }
 }
 
-__device__ __forceinline__ f4 mma(bf8 a, bf8 b, f4 c) { return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0); }
-
-constexpr int BT = 64, BK = 32, BKP = BK + 4;   // tile, k per stage, padded LDS row (16-byte aligned)
-
-template <typename TB>
-__global__ __launch_bounds__(256) void k_cn_bf16(int M, int N, int K, int kchunk, const uint32_t *__restrict__ A,
-                                                 int64_t lda, const cx<TB> *__restrict__ B, int64_t ldb,
-                                                 c32 *__restrict__ part) {
-    __shared__ __align__(16) uint32_t As[BT][BKP];
-    __shared__ __align__(16) uint32_t Bs[BT][BKP];
+// S[j][i] = sum_{k in split s} op(A[i][k]) B[j][k], op = conj when kConj; A [M][lda], B [N][ldb]
+// packed bf16, lda, ldb, kchunk and the K range multiples of 32 (zero beyond the data).
+// kIntoF64: out is complex128 C with C[j][i] += S[j][i] (ldo), one split; else out is
+// complex64 part[s][j][i] (column-major M x N per split).
+template <bool kConj, bool kIntoF64>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_bf16_t128(int M, int N, int Kp, int kchunk, const uint32_t *__restrict__ A,
+                                                   int64_t lda, const uint32_t *__restrict__ B, int64_t ldb,
+                                                   void *__restrict__ out, int64_t ldo) {
+    __shared__ __align__(16) uint32_t Are[T2 * P2], Aim[T2 * P2], Bre[T2 * P2], Bim[T2 * P2];
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     int bx, by, bz;
     xcd_block(bx, by, bz);
-    const int i0 = bx * BT, j0 = by * BT, s = bz;
-    const int kb = s * kchunk, ke = min(K, kb + kchunk);
-    f4 cre[2][2], cim[2][2];
+    const int i0 = bx * T2, j0 = by * T2, s = bz;
+    const int kb = s * kchunk, ke = min(Kp, kb + kchunk);
+    // loader: row tid / 2 of each tile, k half (tid % 2) * 16 of the stage
+    const int lr = tid >> 1, lh = (tid & 1) * 16;
+    const bool arow = i0 + lr < M, brow = j0 + lr < N;
+    const uint32_t *ga = A + (int64_t)(arow ? i0 + lr : 0) * lda + lh;
+    const uint32_t *gb = B + (int64_t)(brow ? j0 + lr : 0) * ldb + lh;
+    u4 pa[4], pb[4];
+    auto fetch = [&](int k0) {
 #pragma unroll
-    for (int a = 0; a < 2; ++a)
+        for (int q = 0; q < 4; ++q) {
+            pa[q] = arow ? *reinterpret_cast<const u4 *>(ga + k0 + 4 * q) : u4{0u, 0u, 0u, 0u};
+            pb[q] = brow ? *reinterpret_cast<const u4 *>(gb + k0 + 4 * q) : u4{0u, 0u, 0u, 0u};
+        }
+    };
+    f4 cre[4][4], cim[4][4];
 #pragma unroll
-        for (int b = 0; b < 2; ++b) cre[a][b] = cim[a][b] = f4{0.f, 0.f, 0.f, 0.f};
-    const int lr = tid >> 2, lk = (tid & 3) * 8;   // loader: row, first of 8 k
-    const int wi = (w & 1) * 32, wj = (w >> 1) * 32;
-    const int gi = i0 + lr, gj = j0 + lr;
-    for (int k0 = kb; k0 < ke; k0 += BK) {
+    for (int r = 0; r < 4; ++r)
 #pragma unroll
-        for (int q = 0; q < 8; ++q) {
-            const int gk = k0 + lk + q;
-            As[lr][lk + q] = (gi < M && gk < ke) ? A[gi * lda + gk] : 0u;
-            Bs[lr][lk + q] = (gj < N && gk < ke) ? pack_c(B[gj * ldb + gk]) : 0u;
+        for (int c = 0; c < 4; ++c) cre[r][c] = cim[r][c] = f4{0.f, 0.f, 0.f, 0.f};
+    const int wi = (w & 1) * 64, wj = (w >> 1) * 64;
+    const int fr = lane & 15, fk = 4 * (lane >> 4);   // fragment row and word offset (8 bf16 = 4 words)
+    if (kb < ke) fetch(kb);
+    for (int k0 = kb; k0 < ke; k0 += BK2) {
+        {
+            u4 re[2], im[2];
+            split16(pa, re, im);
+            const int o = lr * P2 + lh / 2;
+            *reinterpret_cast<u4 *>(&Are[o]) = re[0];
+            *reinterpret_cast<u4 *>(&Are[o + 4]) = re[1];
+            *reinterpret_cast<u4 *>(&Aim[o]) = im[0];
+            *reinterpret_cast<u4 *>(&Aim[o + 4]) = im[1];
+            split16(pb, re, im);
+            *reinterpret_cast<u4 *>(&Bre[o]) = re[0];
+            *reinterpret_cast<u4 *>(&Bre[o + 4]) = re[1];
+            *reinterpret_cast<u4 *>(&Bim[o]) = im[0];
+            *reinterpret_cast<u4 *>(&Bim[o + 4]) = im[1];
         }
         __syncthreads();
-        const int kk = 8 * (lane >> 4);
-        bf8 are[2], aim[2], bre[2], bim[2], naim[2];
+        if (k0 + BK2 < ke) fetch(k0 + BK2);   // in flight while this stage computes
+        bf8 br[4], bi[4];
 #pragma unroll
-        for (int r = 0; r < 2; ++r) {
-            unpack8(&As[wi + 16 * r + (lane & 15)][kk], are[r], aim[r], false);
-            bf8 tmp;
-            unpack8(&As[wi + 16 * r + (lane & 15)][kk], tmp, naim[r], true);
+        for (int c = 0; c < 4; ++c) {
+            const int o = (wj + 16 * c + fr) * P2 + fk;
+            br[c] = as_bf8(*reinterpret_cast<const u4 *>(&Bre[o]));
+            bi[c] = as_bf8(*reinterpret_cast<const u4 *>(&Bim[o]));
         }
 #pragma unroll
-        for (int c = 0; c < 2; ++c) unpack8(&Bs[wj + 16 * c + (lane & 15)][kk], bre[c], bim[c], false);
+        for (int r = 0; r < 4; ++r) {
+            const int o = (wi + 16 * r + fr) * P2 + fk;
+            const u4 ar4 = *reinterpret_cast<const u4 *>(&Are[o]);
+            const u4 ai4 = *reinterpret_cast<const u4 *>(&Aim[o]);
+            const bf8 ar = as_bf8(ar4), ai = as_bf8(ai4), nai = as_bf8(ai4 ^ u4{0x80008000u, 0x80008000u,
+                                                                              0x80008000u, 0x80008000u});
 #pragma unroll
-        for (int r = 0; r < 2; ++r)
-#pragma unroll
-            for (int c = 0; c < 2; ++c) {
-                // conj(a) b = (ar br + ai bi) + i (ar bi - ai br)
-                cre[r][c] = mma(are[r], bre[c], cre[r][c]);
-                cre[r][c] = mma(aim[r], bim[c], cre[r][c]);
-                cim[r][c] = mma(are[r], bim[c], cim[r][c]);
-                cim[r][c] = mma(naim[r], bre[c], cim[r][c]);
+            for (int c = 0; c < 4; ++c) {
+                // conj(a) b = (ar br + ai bi) + i (ar bi - ai br);  a b = (ar br - ai bi) + i (ar bi + ai br)
+                cre[r][c] = mma(ar, br[c], cre[r][c]);
+                cre[r][c] = mma(kConj ? ai : nai, bi[c], cre[r][c]);
+                cim[r][c] = mma(ar, bi[c], cim[r][c]);
+                cim[r][c] = mma(kConj ? nai : ai, br[c], cim[r][c]);
             }
+        }
         __syncthreads();
     }
-    c32 *out = part + (int64_t)s * N * M;
 #pragma unroll
-    for (int r = 0; r < 2; ++r)
+    for (int r = 0; r < 4; ++r)
 #pragma unroll
-        for (int c = 0; c < 2; ++c) {
-            const int jj = j0 + wj + 16 * c + (lane & 15);
+        for (int c = 0; c < 4; ++c) {
+            const int jj = j0 + wj + 16 * c + fr;
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
                 const int ii = i0 + wi + 16 * r + 4 * (lane >> 4) + e;
-                if (ii < M && jj < N) out[(int64_t)jj * M + ii] = c32{cre[r][c][e], cim[r][c][e]};
-            }
-        }
-}
-
-// C[j][g] += sum_i A[j][i] B[i][g]; A complex64 [M][lda], B packed bf16 [K][ldb], C complex128.
-__global__ __launch_bounds__(256) void k_nn_bf16(int M, int G, int K, const c32 *__restrict__ A, int64_t lda,
-                                                 const uint32_t *__restrict__ B, int64_t ldb, z64 *__restrict__ C,
-                                                 int64_t ldc) {
-    __shared__ __align__(16) uint32_t As[BT][BKP];    // [j][i]
-    __shared__ __align__(16) uint32_t Bt[BT][BKP];    // transposed: [g][i]
-    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-    int bx, by, bz;
-    xcd_block(bx, by, bz);
-    const int j0 = bx * BT, g0 = by * BT;
-    f4 cre[2][2], cim[2][2];
-#pragma unroll
-    for (int a = 0; a < 2; ++a)
-#pragma unroll
-        for (int b = 0; b < 2; ++b) cre[a][b] = cim[a][b] = f4{0.f, 0.f, 0.f, 0.f};
-    const int wj = (w & 1) * 32, wg = (w >> 1) * 32;
-    const int ar = tid >> 2, ak = (tid & 3) * 8;      // A loader: row j, 8 consecutive i
-    const int bk = tid >> 3, bg = (tid & 7) * 8;      // B loader: row i, 8 consecutive g
-    for (int k0 = 0; k0 < K; k0 += BK) {
-        {
-            const int gj = j0 + ar;
-#pragma unroll
-            for (int q = 0; q < 8; ++q) {
-                const int gk = k0 + ak + q;
-                As[ar][ak + q] = (gj < M && gk < K) ? pack_c(A[gj * lda + gk]) : 0u;
-            }
-            const int gk = k0 + bk;
-#pragma unroll
-            for (int q = 0; q < 8; ++q) {
-                const int gg = g0 + bg + q;
-                Bt[bg + q][bk] = (gk < K && gg < G) ? B[gk * ldb + gg] : 0u;
-            }
-        }
-        __syncthreads();
-        const int kk = 8 * (lane >> 4);
-        bf8 are[2], aim[2], naim[2], bre[2], bim[2];
-#pragma unroll
-        for (int r = 0; r < 2; ++r) {
-            unpack8(&As[wj + 16 * r + (lane & 15)][kk], are[r], aim[r], false);
-            bf8 tmp;
-            unpack8(&As[wj + 16 * r + (lane & 15)][kk], tmp, naim[r], true);
-        }
-#pragma unroll
-        for (int c = 0; c < 2; ++c) unpack8(&Bt[wg + 16 * c + (lane & 15)][kk], bre[c], bim[c], false);
-#pragma unroll
-        for (int r = 0; r < 2; ++r)
-#pragma unroll
-            for (int c = 0; c < 2; ++c) {
-                // a b = (ar br - ai bi) + i (ar bi + ai br)
-                cre[r][c] = mma(are[r], bre[c], cre[r][c]);
-                cre[r][c] = mma(naim[r], bim[c], cre[r][c]);
-                cim[r][c] = mma(are[r], bim[c], cim[r][c]);
-                cim[r][c] = mma(aim[r], bre[c], cim[r][c]);
-            }
-        __syncthreads();
-    }
-#pragma unroll
-    for (int r = 0; r < 2; ++r)
-#pragma unroll
-        for (int c = 0; c < 2; ++c) {
-            const int gg = g0 + wg + 16 * c + (lane & 15);
-#pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                const int gj = j0 + wj + 16 * r + 4 * (lane >> 4) + e;
-                if (gj < M && gg < G) {
-                    z64 *p = C + (int64_t)gj * ldc + gg;
-                    *p = z64{p->re + (double)cre[r][c][e], p->im + (double)cim[r][c][e]};
+                if (ii < M && jj < N) {
+                    if (kIntoF64) {
+                        z64 *p = static_cast<z64 *>(out) + (int64_t)jj * ldo + ii;
+                        *p = z64{p->re + (double)cre[r][c][e], p->im + (double)cim[r][c][e]};
+                    } else {
+                        static_cast<c32 *>(out)[(int64_t)s * N * M + (int64_t)jj * M + ii] =
+                            c32{cre[r][c][e], cim[r][c][e]};
+                    }
                 }
             }
         }
 }
 
-// packed bf16 copy of a complex128 array
-__global__ void k_pack_bf16(int64_t n, const z64 *__restrict__ in, uint32_t *__restrict__ out) {
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
-        out[i] = pack_c(in[i]);
+// packed bf16 copy of rows [rows][K] (leading dimension ldi) into [rows][ldo], zero for K <= c < ldo
+template <typename T>
+__global__ void k_pack_bf16_rows(int rows, int K, const cx<T> *__restrict__ in, int64_t ldi,
+                                 uint32_t *__restrict__ out, int64_t ldo) {
+    const int64_t n = (int64_t)rows * ldo;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t r = e / ldo;
+        const int c = (int)(e - r * ldo);
+        out[e] = c < K ? pack_c(in[r * ldi + c]) : 0u;
+    }
+}
+
+// out[g][i] = packed bf16 of in[i][g] for i < rows, 0 for rows <= i < ldo (in: complex128 [rows][ldi],
+// g < cols): 32 x 64 tiles through LDS so that reads and writes are both row-contiguous.
+__global__ __launch_bounds__(256) void k_pack_bf16_transpose(int rows, int cols, const z64 *__restrict__ in,
+                                                              int64_t ldi, uint32_t *__restrict__ out, int64_t ldo) {
+    __shared__ uint32_t t[32][64 + 1];
+    const int i0 = blockIdx.y * 32, g0 = blockIdx.x * 64;
+    for (int e = threadIdx.x; e < 32 * 64; e += blockDim.x) {
+        const int r = e / 64, c = e % 64;
+        const int i = i0 + r, g = g0 + c;
+        t[r][c] = (i < rows && g < cols) ? pack_c(in[(int64_t)i * ldi + g]) : 0u;
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < 32 * 64; e += blockDim.x) {
+        const int c = e / 32, r = e % 32;
+        const int i = i0 + r, g = g0 + c;
+        if (g < cols && i < ldo) out[(int64_t)g * ldo + i] = t[r][c];
+    }
 }
 
 // ------------------------------------------------------------ launchers ----
-int pack_bf16(int64_t n, const void *in, void *out, hipStream_t st) {
-    int64_t blocks = std::min<int64_t>(ceil_div64(n, 256), 65536);
+int pack_bf16_transpose(int rows, int cols, const void *in, int64_t ldi, void *out, int64_t ldo, hipStream_t st) {
+    if (rows <= 0 || cols <= 0) return ABACUS_PW_OK;
     KernelTimer kt("convert", st);
-    hipLaunchKernelGGL(k_pack_bf16, dim3((unsigned)std::max<int64_t>(blocks, 1)), dim3(256), 0, st, n,
-                       static_cast<const z64 *>(in), static_cast<uint32_t *>(out));
-    return check_launch("pack_bf16");
+    hipLaunchKernelGGL(k_pack_bf16_transpose, dim3(ceil_div(cols, 64), ceil_div((int)ldo, 32)), dim3(256), 0, st,
+                       rows, cols, static_cast<const z64 *>(in), ldi, static_cast<uint32_t *>(out), ldo);
+    return check_launch("pack_bf16_transpose");
+}
+
+int pack_bf16_rows(int rows, int K, const void *in, int in_is_f64, int64_t ldi, void *out, int64_t ldo,
+                   hipStream_t st) {
+    if (rows <= 0) return ABACUS_PW_OK;
+    const int64_t blocks = std::min<int64_t>(ceil_div64((int64_t)rows * ldo, 256), 65536);
+    KernelTimer kt("convert", st);
+    if (in_is_f64)
+        hipLaunchKernelGGL(k_pack_bf16_rows<double>, dim3((unsigned)blocks), dim3(256), 0, st, rows, K,
+                           static_cast<const z64 *>(in), ldi, static_cast<uint32_t *>(out), ldo);
+    else
+        hipLaunchKernelGGL(k_pack_bf16_rows<float>, dim3((unsigned)blocks), dim3(256), 0, st, rows, K,
+                           static_cast<const c32 *>(in), ldi, static_cast<uint32_t *>(out), ldo);
+    return check_launch("pack_bf16_rows");
+}
+
+// splits of the CN product: enough work-groups to fill the chip (>= 1024), stages of at least 512 k
+static int cn_bf16_chunk(int M, int N, int Kp, int chunk_hint) {
+    if (chunk_hint > 0) return ceil_div(chunk_hint, BK2) * BK2;
+    const int tiles = ceil_div(M, T2) * ceil_div(N, T2);
+    const int want = std::max(1, ceil_div(1024, tiles));
+    const int c = std::max(512, ceil_div(Kp, want));
+    return ceil_div(c, BK2) * BK2;
 }
 
 size_t gemm_cn_bf16_part_bytes(int M, int N, int K, int chunk_hint) {
-    const int tiles = ceil_div(M, BT) * ceil_div(N, BT);
-    int c = chunk_hint > 0 ? ceil_div(chunk_hint, BK) * BK : 0;
-    int ns = c > 0 ? ceil_div(K, c) : std::max(1, 512 / std::max(1, tiles));
-    return (size_t)std::max(ns, 1) * M * N * sizeof(c32) + 256;
+    const int Kp = bf16_ld(K);
+    const int ns = std::max(1, ceil_div(Kp, cn_bf16_chunk(M, N, Kp, chunk_hint)));
+    return (size_t)ns * M * N * sizeof(c32) + 256;
 }
 
-int proj_dapply_bf16(int M, int N, int K, const void *Bpk, int64_t ldb, const void *psi, int psi_is_f64, int64_t ldp,
+int proj_dapply_bf16(int M, int N, int K, const void *Bpk, int64_t ldb, const void *psi_pk, int64_t ldp,
                      const double *dmat, const int *blo, const int *bn, const int *bdoff, void *Q, void *part,
                      int chunk_hint, hipStream_t st) {
     if (M <= 0 || N <= 0) return ABACUS_PW_OK;
-    const int tiles = ceil_div(M, BT) * ceil_div(N, BT);
-    int c = chunk_hint > 0 ? chunk_hint : std::max(512, ceil_div(K, std::max(1, 512 / std::max(1, tiles))));
-    c = ceil_div(c, BK) * BK;
-    const int ns = std::max(1, ceil_div(K, c));
-    dim3 grid(ceil_div(M, BT), ceil_div(N, BT), ns);
+    const int Kp = bf16_ld(K);
+    const int c = cn_bf16_chunk(M, N, Kp, chunk_hint);
+    const int ns = std::max(1, ceil_div(Kp, c));
+    dim3 grid(ceil_div(M, T2), ceil_div(N, T2), ns);
     {
         KernelTimer kt("gemm_cn_bf16", st);
-        if (psi_is_f64)
-            hipLaunchKernelGGL(k_cn_bf16<double>, grid, dim3(256), 0, st, M, N, K, c,
-                               static_cast<const uint32_t *>(Bpk), ldb, static_cast<const z64 *>(psi), ldp,
-                               static_cast<c32 *>(part));
-        else
-            hipLaunchKernelGGL(k_cn_bf16<float>, grid, dim3(256), 0, st, M, N, K, c,
-                               static_cast<const uint32_t *>(Bpk), ldb, static_cast<const c32 *>(psi), ldp,
-                               static_cast<c32 *>(part));
+        hipLaunchKernelGGL((k_bf16_t128<true, false>), grid, dim3(256), 0, st, M, N, Kp, c,
+                           static_cast<const uint32_t *>(Bpk), ldb, static_cast<const uint32_t *>(psi_pk), ldp, part,
+                           (int64_t)0);
         APW_TRY(check_launch("gemm_cn_bf16"));
     }
     return reduce_dapply_f32(M, N, ns, part, dmat, blo, bn, bdoff, Q, st);
 }
 
-int gemm_nn_bf16_into_f64(int M, int G, int K, const void *A, int64_t lda, const void *Bpk, int64_t ldb, void *C,
+int gemm_nn_bf16_into_f64(int N, int G, int K, const void *Apk, int64_t lda, const void *BTpk, int64_t ldbt, void *C,
                           int64_t ldc, hipStream_t st) {
-    if (M <= 0 || G <= 0) return ABACUS_PW_OK;
-    dim3 grid(ceil_div(M, BT), ceil_div(G, BT));
+    if (N <= 0 || G <= 0) return ABACUS_PW_OK;
+    const int Kp = bf16_ld(K);
+    dim3 grid(ceil_div(G, T2), ceil_div(N, T2), 1);
     KernelTimer kt("gemm_nn_bf16", st);
-    hipLaunchKernelGGL(k_nn_bf16, grid, dim3(256), 0, st, M, G, K, static_cast<const c32 *>(A), lda,
-                       static_cast<const uint32_t *>(Bpk), ldb, static_cast<z64 *>(C), ldc);
+    hipLaunchKernelGGL((k_bf16_t128<false, true>), grid, dim3(256), 0, st, G, N, Kp, Kp,
+                       static_cast<const uint32_t *>(BTpk), ldbt, static_cast<const uint32_t *>(Apk), lda, C, ldc);
     return check_launch("gemm_nn_bf16");
 }
 

@@ -18,6 +18,13 @@ int default_band_batch(const Plan &P, int nb) {
     return std::max(1, std::min(bb, nb));
 }
 
+// Start (in packed words per projector row) of k-point k's block of the padded bf16 beta copy.
+int64_t bf16_offset(const Plan &P, int k) {
+    int64_t o = 0;
+    for (int q = 0; q < k; ++q) o += bf16_ld(P.npw[q]);
+    return o;
+}
+
 // Reduced-precision copies of V and beta, refreshed unless the caller marks the operator static.
 int operator_copies(const abacus_pw_problem &p, Plan &P, bool need_v32, bool need_b32, hipStream_t st, bool need_bf) {
     const bool stat = (p.flags & ABACUS_PW_STATIC_OPERATOR) != 0;
@@ -33,9 +40,20 @@ int operator_copies(const abacus_pw_problem &p, Plan &P, bool need_v32, bool nee
         P.beta32_src = p.beta;
     }
     if (need_bf && P.nproj > 0 && !(stat && P.betabf_src == p.beta)) {
-        const int64_t n = (int64_t)P.nproj * P.npw_total;
-        APW_TRY(P.betabf.ensure(sizeof(uint32_t) * (size_t)n));
-        APW_TRY(pack_bf16(n, p.beta, P.betabf.ptr, st));
+        // per k a [nproj][bf16_ld(npw_k)] block of packed bf16 pairs, rows zero-padded
+        APW_TRY(P.betabf.ensure(sizeof(uint32_t) * (size_t)P.nproj * (size_t)bf16_offset(P, P.nk)));
+        for (int k = 0; k < P.nk; ++k) {
+            const int npw = P.npw[k];
+            APW_TRY(pack_bf16_rows(P.nproj, npw, static_cast<const z64 *>(p.beta) + (size_t)P.nproj * P.pw_off[k], 1,
+                                   npw, P.betabf.as<uint32_t>() + (size_t)P.nproj * bf16_offset(P, k), bf16_ld(npw),
+                                   st));
+        }
+        // and per k the transposed [npw_k][bf16_ld(nproj)] block, projector index contiguous
+        const int ldq = bf16_ld(P.nproj);
+        APW_TRY(P.betabfT.ensure(sizeof(uint32_t) * (size_t)ldq * (size_t)P.npw_total));
+        for (int k = 0; k < P.nk; ++k)
+            APW_TRY(pack_bf16_transpose(P.nproj, P.npw[k], static_cast<const z64 *>(p.beta) + (size_t)P.nproj * P.pw_off[k],
+                                        P.npw[k], P.betabfT.as<uint32_t>() + (size_t)ldq * P.pw_off[k], ldq, st));
         P.betabf_src = p.beta;
     }
     return ABACUS_PW_OK;
@@ -104,8 +122,13 @@ int apply_h_range(const abacus_pw_problem &p, Plan &P, int k0, int k1, int prec,
     const size_t gb = gemm_prec == 0 ? 16 : 8;   // bytes per element of Q (complex64 in the BF16 mode)
     const size_t qk = (size_t)nb * P.nproj * gb; // Q bytes per k-point
     APW_TRY(P.projq.ensure(qk * (k1 - k0)));
-    if (bf)
-        APW_TRY(P.gemm_part.ensure(gemm_cn_bf16_part_bytes(P.nproj, nb, P.max_npw, g_splitk_chunk)));
+    if (bf) {
+        size_t pb = 0;   // the split count depends on each sphere's size
+        for (int k = k0; k < k1; ++k) pb = std::max(pb, gemm_cn_bf16_part_bytes(P.nproj, nb, P.npw[k], g_splitk_chunk));
+        APW_TRY(P.gemm_part.ensure(pb));
+        APW_TRY(P.psibf.ensure(sizeof(uint32_t) * (size_t)nb * bf16_ld(P.max_npw)));
+        APW_TRY(P.qbf.ensure(sizeof(uint32_t) * (size_t)nb * bf16_ld(P.nproj)));
+    }
     else
         APW_TRY(P.gemm_part.ensure(gemm_cn_part_bytes(P.nproj, nb, P.max_npw, (int)gb, g_splitk_chunk)));
     if (prec == ABACUS_PW_MIXED_FP32) APW_TRY(P.tmp_io.ensure((size_t)nb * P.max_npw * 8));
@@ -119,7 +142,7 @@ int apply_h_range(const abacus_pw_problem &p, Plan &P, int k0, int k1, int prec,
         APW_TRY(order(ss->fork, st, gs));
     }
     auto beta_k = [&](const KTables &K) -> const void * {
-        if (bf) return P.betabf.as<char>() + (size_t)P.nproj * K.pw_off * 4;
+        if (bf) return P.betabf.as<char>() + (size_t)P.nproj * bf16_offset(P, (int)(&K - P.k.data())) * 4;
         return gemm_prec == 0 ? static_cast<const void *>(static_cast<const char *>(p.beta) + (size_t)P.nproj * K.pw_off * 16)
                               : static_cast<const void *>(P.beta32.as<char>() + (size_t)P.nproj * K.pw_off * 8);
     };
@@ -130,8 +153,10 @@ int apply_h_range(const abacus_pw_problem &p, Plan &P, int k0, int k1, int prec,
         void *qk_ptr = P.projq.as<char>() + qk * (k - k0);
         const void *bk = beta_k(K);
         if (bf) {
-            APW_TRY(proj_dapply_bf16(P.nproj, nb, K.npw, bk, K.npw, xk, 1, K.npw, p.dmat, P.proj_blk_lo, P.proj_blk_n,
-                                     P.proj_blk_doff, qk_ptr, P.gemm_part.ptr, g_splitk_chunk, gs));
+            const int ldk = bf16_ld(K.npw);
+            APW_TRY(pack_bf16_rows(nb, K.npw, xk, io_prec == 0 ? 1 : 0, K.npw, P.psibf.ptr, ldk, gs));
+            APW_TRY(proj_dapply_bf16(P.nproj, nb, K.npw, bk, ldk, P.psibf.ptr, ldk, p.dmat, P.proj_blk_lo,
+                                     P.proj_blk_n, P.proj_blk_doff, qk_ptr, P.gemm_part.ptr, g_splitk_chunk, gs));
             continue;
         }
         const void *xg = xk;
@@ -150,8 +175,12 @@ int apply_h_range(const abacus_pw_problem &p, Plan &P, int k0, int k1, int prec,
             char *yk = static_cast<char *>(hpsi) + ((size_t)nb * (K.pw_off - P.pw_off[k0]) + (size_t)b0 * K.npw) * ib;
             const char *qb = P.projq.as<char>() + qk * (k - k0) + (size_t)b0 * P.nproj * gb;
             const void *bk = beta_k(K);
-            if (bf)
-                APW_TRY(gemm_nn_bf16_into_f64(bbt, K.npw, P.nproj, qb, P.nproj, bk, K.npw, yk, K.npw, s));
+            if (bf) {
+                const int ldq = bf16_ld(P.nproj);
+                APW_TRY(pack_bf16_rows(bbt, P.nproj, qb, 0, P.nproj, P.qbf.ptr, ldq, s));
+                const uint32_t *btk = P.betabfT.as<uint32_t>() + (size_t)ldq * K.pw_off;
+                APW_TRY(gemm_nn_bf16_into_f64(bbt, K.npw, P.nproj, P.qbf.ptr, ldq, btk, ldq, yk, K.npw, s));
+            }
             else if (prec == ABACUS_PW_MIXED_FP32)
                 APW_TRY(gemm_nn_f32_into_f64(bbt, K.npw, P.nproj, qb, P.nproj, bk, K.npw, yk, K.npw, 1.0, 1.0, s));
             else

@@ -86,7 +86,10 @@ struct Plan {
     // reduced-precision copies of operator data (refreshed unless STATIC)
     DeviceBuffer vloc32;
     DeviceBuffer beta32;      // complex64 beta
-    DeviceBuffer betabf;      // bf16 planar beta (re block, im block) per k
+    DeviceBuffer betabf;      // packed bf16 beta per k, rows padded to bf16_ld(npw_k)
+    DeviceBuffer betabfT;     // packed bf16 beta transposed per k: [npw_k][bf16_ld(nproj)]
+    DeviceBuffer psibf;       // packed bf16 psi of one k-point (MIXED_BF16 projection)
+    DeviceBuffer qbf;         // packed bf16 Q = D P of one band batch (MIXED_BF16 accumulation)
     const void *vloc32_src = nullptr, *beta32_src = nullptr, *betabf_src = nullptr;
 
     // work space
