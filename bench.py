@@ -15,7 +15,7 @@ oracle timed on this host.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-davidson] [--no-cg]
                       [--no-batched] [--no-autotune] [--no-density] [--no-backward] [--no-chebyshev]
-                      [--no-force]
+                      [--no-force] [--no-c4]
 """
 from __future__ import annotations
 
@@ -33,6 +33,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0           # MI355X HBM3E, datasheet
+BF16_PEAK_TFLOPS = 2500.0       # MI355X dense BF16 MFMA
 FP64_PEAK_TFLOPS = 78.6         # MI355X dense FP64 (vector = matrix)
 FP32_PEAK_TFLOPS = 157.3
 WORKLOAD = "C2"
@@ -54,6 +55,7 @@ def parse():
     ap.add_argument("--no-backward", action="store_true")
     ap.add_argument("--no-chebyshev", action="store_true")
     ap.add_argument("--no-force", action="store_true")
+    ap.add_argument("--no-c4", action="store_true")
     ap.add_argument("--traffic-probe", action="store_true",
                     help="run a plain 256 MiB copy and a few H psi steps only (for counter collection)")
     return ap.parse_args()
@@ -324,6 +326,8 @@ def main():
 
     if not args.no_density:
         out["density"] = density_times(B, W, dev, prob, dp, x64, args.steps)
+    if not args.no_c4:
+        out["mixed_precision_c4"] = c4_times(B, W, dev)
     if not args.no_force:
         out["force_nl"] = force_times(B, W, dev, prob, dp, x64, args.steps)
     if not args.no_chebyshev:
@@ -397,6 +401,59 @@ def density_times(B, W, dev, prob, dp, x, steps):
         by = bands * cb * S + 2 * 8 * 8 * N
         r["alg_bytes"] = by
         r["gbs"] = by / (r["avg_ms"] * 1e-3) / 1e9
+    return res
+
+
+def c4_times(B, W, dev):
+    """The mixed-precision workload (C4: cubic a=30 bohr, ecutwfc=50 Ry, 128^3, 161,235 PW,
+    256 atoms x 9 projectors (s+p+d, full D blocks), 1024 bands): one H psi in FP64, FP32,
+    MIXED_FP32 (FP32 transforms and GEMMs, complex128 psi) and MIXED_BF16 (FP32 transforms,
+    bf16 projector GEMMs with FP32 accumulation). GEMM rates count 8 nproj nb npw flops per
+    product against the peak of the product's own precision; errors are relative max-norm
+    against the FP64 result of the same GPU run."""
+    import torch
+    prob = W.make_problem("C4")
+    B.set_tuning()
+    dp = B.DeviceProblem(prob, device=dev, static=True)
+    x = torch.from_numpy(prob.psi).to(dev)
+    nb, npw = prob.nb, int(prob.npw[0])
+    flops = 8.0 * prob.nproj * nb * npw
+    res = {"workload": "C4: cubic a=30 bohr, ecutwfc=50 Ry, 128^3, 161235 PW, Gamma, 256 atoms x 9 projectors, "
+                       "1024 bands"}
+    ref = None
+    steps = 3
+    for name, prec in (("fp64", B.FP64), ("fp32", B.FP32), ("mixed_fp32", B.MIXED_FP32), ("mixed_bf16", B.MIXED_BF16)):
+        xx = x.to(torch.complex64) if prec == B.FP32 else x
+        y = torch.empty_like(xx)
+        B.apply_h(dp, xx, prec, out=y)
+        torch.cuda.synchronize()
+        B.profile_read()
+        B.profile_enable(True)
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        for _ in range(steps):
+            B.apply_h(dp, xx, prec, out=y)
+        b.record()
+        torch.cuda.synchronize()
+        B.profile_enable(False)
+        kern = B.profile_read()
+        ms = a.elapsed_time(b) / steps
+        row = {"ms_per_h_psi": ms, "band_applies_per_s": nb / (ms * 1e-3)}
+        for kn, (n, tot) in kern.items():
+            if kn.startswith("gemm_") and "reduce" not in kn:
+                avg = tot / n
+                pk = BF16_PEAK_TFLOPS if kn.endswith("bf16") else (FP64_PEAK_TFLOPS if prec == B.FP64 else FP32_PEAK_TFLOPS)
+                tf = flops / (avg * 1e-3) / 1e12
+                row[kn] = {"ms": avg, "tflops": tf, "peak": pk, "frac": tf / pk}
+        yc = y.to(torch.complex128)
+        if ref is None:
+            ref = yc
+            res["fp64_max_abs"] = float(ref.abs().max())
+        else:
+            row["rel_err_vs_fp64"] = float((yc - ref).abs().max() / ref.abs().max())
+            row["speedup_vs_fp64"] = res["fp64"]["ms_per_h_psi"] / ms
+        res[name] = row
+        del y, yc
     return res
 
 
