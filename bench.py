@@ -675,7 +675,8 @@ def cg_times(B, W, dev, dav):
 
 
 def davidson_times(B, W, dev):
-    """Block Davidson on the benchmark workload to a 1e-8 residual, FP64 and mixed."""
+    """Block Davidson on the benchmark workload to a 1e-8 residual: FP64, and the two mixed
+    modes (reduced-precision phase with FP32 or bf16 products, then FP64 refinement)."""
     import torch
     res = {}
     prob = W.make_problem(WORKLOAD)
@@ -683,7 +684,7 @@ def davidson_times(B, W, dev):
     x = torch.from_numpy(prob.psi).to(dev)
     B.apply_h(dp, x)   # plan and work space built outside the timed solves
     torch.cuda.synchronize()
-    for name, prec in (("fp64", B.FP64), ("mixed_fp32", B.MIXED_FP32)):
+    for name, prec in (("fp64", B.FP64), ("mixed_fp32", B.MIXED_FP32), ("mixed_bf16", B.MIXED_BF16)):
         x = torch.from_numpy(prob.psi).to(dev)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -700,8 +701,12 @@ def davidson_times(B, W, dev):
         res["mixed_vs_fp64_max_eig_diff"] = float(np.max(np.abs(np.array(res["fp64_eig"]) -
                                                                np.array(res["mixed_fp32_eig"]))))
         res["mixed_speedup"] = res["fp64"]["s_per_kpoint"] / res["mixed_fp32"]["s_per_kpoint"]
-    res.pop("fp64_eig", None)
-    res.pop("mixed_fp32_eig", None)
+    if "fp64_eig" in res and "mixed_bf16_eig" in res:
+        res["mixed_bf16_vs_fp64_max_eig_diff"] = float(np.max(np.abs(np.array(res["fp64_eig"]) -
+                                                                    np.array(res["mixed_bf16_eig"]))))
+        res["mixed_bf16_speedup"] = res["fp64"]["s_per_kpoint"] / res["mixed_bf16"]["s_per_kpoint"]
+    for key in ("fp64_eig", "mixed_fp32_eig", "mixed_bf16_eig"):
+        res.pop(key, None)
     return res
 
 

@@ -18,7 +18,8 @@
 //
 // Mixed modes: a first Davidson phase applies H in reduced precision (FP32
 // transforms, FP32 or BF16 projector GEMMs, complex128 vectors) and forms the
-// subspace matrix V^H H V with FP32 products (FP32 MFMA, FP64 split-K sum);
+// subspace matrix V^H H V with FP32 (MIXED_FP32) or bf16 (MIXED_BF16) products
+// on MFMA with FP32 accumulation and an FP64 split-K sum;
 // orthonormalisation, Cholesky, Rayleigh-Ritz and residual norms stay FP64.
 // Then an FP64 phase refines the Ritz vectors to tol with the FP64 H.
 #include <algorithm>
@@ -36,7 +37,7 @@ namespace apw {
 namespace {
 
 struct Buffers {
-    DeviceBuffer V, HV, Xc, Wc, R, Y, Hs, Hw, coef, C, G, Linv, part, theta, rn2, ek, n0, n1, act, idx, info, heev;
+    DeviceBuffer V, HV, Xc, Wc, R, Y, Hs, Hw, coef, C, G, Linv, part, theta, rn2, ek, n0, n1, act, idx, info, heev, bfs;
 };
 
 int d2h(void *dst, const void *src, size_t bytes, hipStream_t st) {
@@ -154,10 +155,14 @@ int davidson_k(const abacus_pw_problem &p, Plan &P, int k, int hprec, int nb, z6
     APW_TRY(cholqr_rows(nb, npw, Xc, Y, b, 1, st));
     APW_TRY(apply_h_k(p, P, k, hprec, nb, Xc, Wc, st, false));
     // subspace projections V^H (H V): FP32 products in a reduced-precision phase, else FP64
+    // subspace projections V^H (H V): FP64, or in the reduced-precision phase FP32 (MIXED_FP32) or
+    // bf16 (MIXED_BF16) products with FP32 accumulation
+    if (hprec == ABACUS_PW_MIXED_BF16) APW_TRY(b.bfs.ensure(gemm_cn_bf16_of_f64_bytes(nmax, nb, npw)));
     auto project = [&](int M, int N, const z64 *A, const z64 *B, z64 *Cout, int ldc) -> int {
-        return hprec == ABACUS_PW_FP64 ? gemm_cn(0, M, N, npw, A, npw, B, npw, Cout, ldc, 1.0, 0.0, b.part.ptr, 0, st)
-                                       : gemm_cn_f32_of_f64(M, N, npw, A, npw, B, npw, Cout, ldc, 1.0, 0.0, b.part.ptr,
-                                                            0, st);
+        if (hprec == ABACUS_PW_FP64) return gemm_cn(0, M, N, npw, A, npw, B, npw, Cout, ldc, 1.0, 0.0, b.part.ptr, 0, st);
+        if (hprec == ABACUS_PW_MIXED_BF16)
+            return gemm_cn_bf16_of_f64(M, N, npw, A, npw, B, npw, Cout, ldc, b.bfs.ptr, st);
+        return gemm_cn_f32_of_f64(M, N, npw, A, npw, B, npw, Cout, ldc, 1.0, 0.0, b.part.ptr, 0, st);
     };
     APW_TRY(project(nb, nb, Xc, Wc, C, nb));
     APW_TRY(dav_hs_append(0, nb, C, nb, Hs, nmax, st));

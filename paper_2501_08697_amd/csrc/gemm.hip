@@ -393,6 +393,16 @@ static int gemm_cn_t(int M, int N, int K, const void *A, int64_t lda, const void
     return check_launch("gemm_reduce");
 }
 
+int reduce_parts_f32_to_f64(int M, int N, int nsplit, const void *part, void *C, int64_t ldc, double alpha,
+                            double beta, hipStream_t st) {
+    if (M <= 0 || N <= 0) return ABACUS_PW_OK;
+    const int64_t tot = (int64_t)M * N;
+    KernelTimer kt("gemm_reduce", st);
+    hipLaunchKernelGGL((k_reduce<float, double>), dim3((unsigned)ceil_div64(tot, 256)), dim3(256), 0, st, M, N, nsplit,
+                       static_cast<const c32 *>(part), static_cast<z64 *>(C), ldc, alpha, beta);
+    return check_launch("gemm_reduce");
+}
+
 int gemm_cn_f32_of_f64(int M, int N, int K, const void *A, int64_t lda, const void *B, int64_t ldb, void *C,
                        int64_t ldc, double alpha, double beta, void *part, int chunk_hint, hipStream_t st) {
     return gemm_cn_t<float, double>(M, N, K, A, lda, B, ldb, C, ldc, alpha, beta, part, chunk_hint, st);

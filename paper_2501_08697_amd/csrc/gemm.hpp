@@ -53,6 +53,14 @@ size_t gemm_cn_bf16_part_bytes(int M, int N, int K, int chunk_hint);
 int proj_dapply_bf16(int M, int N, int K, const void *Bpk, int64_t ldb, const void *psi_pk, int64_t ldp,
                      const double *dmat, const int *blo, const int *bn, const int *bdoff, void *Q, void *part,
                      int chunk_hint, hipStream_t st);
+// C = alpha sum_s part[s] + beta C: complex64 split-K partials [nsplit][N][M] into complex128 C (ldc).
+int reduce_parts_f32_to_f64(int M, int N, int nsplit, const void *part, void *C, int64_t ldc, double alpha,
+                            double beta, hipStream_t st);
+// C = A^H B (M x N, ldc) for complex128 rows A [M][lda], B [N][ldb] of length K, computed with both
+// operands rounded to bf16 and FP32 accumulation; scratch of gemm_cn_bf16_of_f64_bytes(M, N, K) bytes.
+size_t gemm_cn_bf16_of_f64_bytes(int M, int N, int K);
+int gemm_cn_bf16_of_f64(int M, int N, int K, const void *A, int64_t lda, const void *B, int64_t ldb, void *C,
+                        int64_t ldc, void *scratch, hipStream_t st);
 // out[g][i] = in[i][g] (complex128 [rows][ldi], g < cols) as packed bf16, zero for rows <= i < ldo.
 int pack_bf16_transpose(int rows, int cols, const void *in, int64_t ldi, void *out, int64_t ldo, hipStream_t st);
 // C[j][g] += sum_i A[j][i] B[i][g] for j < N, g < G, i < K: Apk packed bf16 A [N][lda], BTpk packed bf16

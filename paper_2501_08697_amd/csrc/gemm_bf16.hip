@@ -250,6 +250,34 @@ int proj_dapply_bf16(int M, int N, int K, const void *Bpk, int64_t ldb, const vo
     return reduce_dapply_f32(M, N, ns, part, dmat, blo, bn, bdoff, Q, st);
 }
 
+// Bound over every M' <= M, N' <= N: a chunk is never below 512 k, so at most ceil(Kp / 512) splits.
+size_t gemm_cn_bf16_of_f64_bytes(int M, int N, int K) {
+    const int Kp = bf16_ld(K);
+    const size_t packs = sizeof(uint32_t) * (size_t)(M + N) * Kp;
+    return (packs + 255) / 256 * 256 + (size_t)ceil_div(Kp, 512) * M * N * sizeof(c32) + 256;
+}
+
+int gemm_cn_bf16_of_f64(int M, int N, int K, const void *A, int64_t lda, const void *B, int64_t ldb, void *C,
+                        int64_t ldc, void *scratch, hipStream_t st) {
+    if (M <= 0 || N <= 0) return ABACUS_PW_OK;
+    const int Kp = bf16_ld(K);
+    uint32_t *apk = static_cast<uint32_t *>(scratch);
+    uint32_t *bpk = apk + (size_t)M * Kp;
+    void *part = static_cast<char *>(scratch) + (sizeof(uint32_t) * (size_t)(M + N) * Kp + 255) / 256 * 256;
+    APW_TRY(pack_bf16_rows(M, K, A, 1, lda, apk, Kp, st));
+    APW_TRY(pack_bf16_rows(N, K, B, 1, ldb, bpk, Kp, st));
+    const int c = cn_bf16_chunk(M, N, Kp, 0);
+    const int ns = std::max(1, ceil_div(Kp, c));
+    dim3 grid(ceil_div(M, T2), ceil_div(N, T2), ns);
+    {
+        KernelTimer kt("gemm_cn_bf16", st);
+        hipLaunchKernelGGL((k_bf16_t128<true, false>), grid, dim3(256), 0, st, M, N, Kp, c, apk, (int64_t)Kp, bpk,
+                           (int64_t)Kp, part, (int64_t)0);
+        APW_TRY(check_launch("gemm_cn_bf16"));
+    }
+    return reduce_parts_f32_to_f64(M, N, ns, part, C, ldc, 1.0, 0.0, st);
+}
+
 int gemm_nn_bf16_into_f64(int N, int G, int K, const void *Apk, int64_t lda, const void *BTpk, int64_t ldbt, void *C,
                           int64_t ldc, hipStream_t st) {
     if (N <= 0 || G <= 0) return ABACUS_PW_OK;

@@ -147,6 +147,16 @@ def test_mixed_bf16_refines_to_fp64():
     check_vectors(p, psi, ebf, 16, 1.5e-10)
 
 
+def test_c2_mixed_bf16_matches_fp64():
+    """C2 cell, 16 bands: bf16 projector and subspace products in the first phase, FP64 refinement."""
+    p = W.make_problem("C2", nb=16)
+    e64, _, _, _, st64 = gpu_davidson(p, 1e-9, 300)
+    ebf, psi, res, its, st = gpu_davidson(p, 1e-9, 300, prec=B().MIXED_BF16)
+    assert st == 0 and st64 == 0
+    np.testing.assert_allclose(ebf, e64, atol=1e-11)
+    check_vectors(p, psi, ebf, 16, 1.5e-9)
+
+
 def test_rejects_bad_sizes():
     b = B()
     p = W.make_problem(W.tiny_config(fft=8, ecut=5.0, nb=2))
