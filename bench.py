@@ -15,7 +15,7 @@ oracle timed on this host.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-davidson] [--no-cg]
                       [--no-batched] [--no-autotune] [--no-density] [--no-backward] [--no-chebyshev]
-                      [--no-force] [--no-c4]
+                      [--no-force] [--no-c4] [--c3]
 """
 from __future__ import annotations
 
@@ -56,6 +56,8 @@ def parse():
     ap.add_argument("--no-chebyshev", action="store_true")
     ap.add_argument("--no-force", action="store_true")
     ap.add_argument("--no-c4", action="store_true")
+    ap.add_argument("--c3", action="store_true",
+                    help="also run the batched leg on the full C3 workload (8 k-points x 512 bands, 120^3; ~2 min)")
     ap.add_argument("--traffic-probe", action="store_true",
                     help="run a plain 256 MiB copy and a few H psi steps only (for counter collection)")
     return ap.parse_args()
@@ -340,6 +342,8 @@ def main():
         out["cg_vs_davidson"] = cg_times(B, W, dev, out.get("davidson"))
     if not args.no_batched:
         out["batched_kpoints"] = batched_times(B, W, dev, max(5, args.steps // 4))
+    if args.c3:
+        out["batched_kpoints_c3"] = batched_times(B, W, dev, 3, "C3")
 
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(prob)
@@ -556,7 +560,7 @@ def backward_times(B, W, dev, steps):
     (2 nb cb S per call) plus its partial grids (G = 8 of N doubles, read and written once
     per band batch)."""
     import torch
-    prob = W.make_problem("C5")
+    prob = W.make_problem(workload)
     nb, nk = prob.nb, prob.nk
     B.set_tuning()
     dp = B.DeviceProblem(prob, device=dev, static=True)
@@ -598,8 +602,9 @@ def backward_times(B, W, dev, steps):
     return res
 
 
-def batched_times(B, W, dev, steps):
-    """H psi over four uneven k-points (Gamma, X, M, R; 96^3; 256 bands each; 512 projectors).
+def batched_times(B, W, dev, steps, workload="C5"):
+    """H psi over uneven k-points: C5 (Gamma, X, M, R; 96^3; 256 bands each; 512 projectors), or
+    C3 (the {0,1/2}^3 grid, eight spheres of 115,096 - 115,396 PW; 120^3; 512 bands each; 864 projectors).
 
     Plain FP64 with one call per k-point, against every k-point in one call
     (one launch per pass per band batch), that call replayed from a HIP graph,
@@ -607,7 +612,7 @@ def batched_times(B, W, dev, steps):
     band-applies per second over all k-points.
     """
     import torch
-    prob = W.make_problem("C5")
+    prob = W.make_problem(workload)
     nb, nk = prob.nb, prob.nk
     B.set_tuning()
     dp = B.DeviceProblem(prob, device=dev, static=True)
@@ -633,8 +638,10 @@ def batched_times(B, W, dev, steps):
         torch.cuda.synchronize()
         return a.elapsed_time(b) / steps
 
-    res = {"workload": "C5: cubic a=24 bohr, ecutwfc=35 Ry, 96^3, k = G, X, M, R (npw " +
-                       "/".join(str(int(n)) for n in prob.npw) + "), 256 bands each, 128 atoms x 4 projectors"}
+    desc = {"C5": "C5: cubic a=24 bohr, ecutwfc=35 Ry, 96^3, k = G, X, M, R", "C3": "C3: cubic a=30 bohr, "
+            "ecutwfc=40 Ry, 120^3, k on the {0,1/2}^3 grid"}[workload]
+    res = {"workload": desc + " (npw " + "/".join(str(int(n)) for n in prob.npw) + f"), {nb} bands each, "
+                       f"{prob.natom} atoms x {prob.nproj // prob.natom} projectors"}
     t_perk = timed(lambda: [B.apply_h(dk, xk, out=yk) for dk, xk, yk in subs])
     y = torch.empty_like(x)
     t_batch = timed(lambda: B.apply_h(dp, x, out=y))

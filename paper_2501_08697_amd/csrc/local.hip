@@ -175,14 +175,14 @@ __global__ __launch_bounds__(256) void k_xpass(cx<T> *__restrict__ slab, int nsl
     const bool has_ka = tid < w3 * A, has_jb = tid < w3 * B;
     cx<T> *base = slab + (int64_t)j2 * N3 + c0 + c;
     T vr[A];
-    int64_t src[B];
+    int src[B];   // slab offset of each row (< 2^31: at most 128^3 points per band)
 #pragma unroll
     for (int ja = 0; ja < A; ++ja)
         vr[ja] = has_jb ? static_cast<T>(vloc[(int64_t)(jb + B * ja) * plane + (int64_t)j2 * N3 + c0 + c]) : T(0);
 #pragma unroll
     for (int kb = 0; kb < B; ++kb) {
         const int sl = has_ka ? r2s[B * ka + kb] : -1;
-        src[kb] = sl >= 0 ? sl * plane : -1;
+        src[kb] = sl >= 0 ? (int)(sl * plane) : -1;
     }
     cx<T> pre[B];
 #pragma unroll
@@ -474,11 +474,11 @@ __global__ __launch_bounds__(256) void k_gradv_x(const cx<T> *__restrict__ slab_
     const int ka = tid / w3, jb = tid / w3;
     const bool has_ka = tid < w3 * A, has_jb = tid < w3 * B;
     const int64_t col = (int64_t)j2 * N3 + c0 + c;
-    int64_t src[B];
+    int src[B];   // slab offset of each row (< 2^31: at most 128^3 points per band)
 #pragma unroll
     for (int kb = 0; kb < B; ++kb) {
         const int sl = has_ka ? r2s[B * ka + kb] : -1;
-        src[kb] = sl >= 0 ? sl * plane : -1;
+        src[kb] = sl >= 0 ? (int)(sl * plane) : -1;
     }
     // source t: psi (t even) or dY (t odd) of band bs + t / 2
     const int nt = 2 * max(0, be - bs);
@@ -574,11 +574,11 @@ __global__ __launch_bounds__(256) void k_density_x(const cx<T> *__restrict__ sla
     const int ka = tid / w3, jb = tid / w3;
     const bool has_ka = tid < w3 * A, has_jb = tid < w3 * B;
     const cx<T> *base = slab + (int64_t)j2 * N3 + c0 + c;
-    int64_t src[B];
+    int src[B];   // slab offset of each row (< 2^31: at most 128^3 points per band)
 #pragma unroll
     for (int kb = 0; kb < B; ++kb) {
         const int sl = has_ka ? r2s[B * ka + kb] : -1;
-        src[kb] = sl >= 0 ? sl * plane : -1;
+        src[kb] = sl >= 0 ? (int)(sl * plane) : -1;
     }
     double acc[A];
 #pragma unroll
