@@ -560,7 +560,7 @@ def backward_times(B, W, dev, steps):
     (2 nb cb S per call) plus its partial grids (G = 8 of N doubles, read and written once
     per band batch)."""
     import torch
-    prob = W.make_problem(workload)
+    prob = W.make_problem("C5")
     nb, nk = prob.nb, prob.nk
     B.set_tuning()
     dp = B.DeviceProblem(prob, device=dev, static=True)
