@@ -219,3 +219,31 @@ def test_overlap_is_bitwise_one_stream(prec):
     assert np.array_equal(out[1], out[2])
     tol = {0: 1e-12, 1: 1e-5, 2: 2e-2, 3: 1e-5}[prec]
     assert rel(out[1], oracle.apply_h(p, p.psi)) < tol
+
+
+def test_bf16_uneven_kpoints_odd_projector_count():
+    """Two k-points with different spheres and 27 projectors (padded to 32 in the bf16 copies):
+    the nonlocal term against the oracle, bound 2e-2."""
+    p = W.make_problem(W.tiny_config(fft=12, ecut=10.0, kfrac=((0.0, 0.0, 0.0), (0.5, 0.25, 0.0)), lmax=2, natom=3,
+                                     nb=5, dfull=True))
+    assert p.nproj == 27 and p.npw[0] != p.npw[1]   # 123 and 112 plane waves
+    q = dataclasses.replace(p, vloc=np.zeros_like(p.vloc))
+    kin = np.concatenate([np.tile(oracle.kinetic(q, k), q.nb) for k in range(q.nk)])
+    nl_ref = oracle.apply_h(q, q.psi) - kin * q.psi
+    nl = gpu_apply(q, prec=B().MIXED_BF16) - kin * q.psi
+    e = rel(nl, nl_ref)
+    print(f"bf16 nonlocal relative error (two k, 27 projectors) {e:.3e}", flush=True)
+    assert e < 2e-2
+
+
+def test_c5_bf16_against_fp64():
+    """Four uneven k-points, 512 projectors, 256 bands: MIXED_BF16 H psi against the FP64 result of
+    the same GPU (itself checked against the oracle), bound 2e-2."""
+    p = W.make_problem("C5")
+    b = B()
+    dp = b.DeviceProblem(p)
+    y64 = gpu_apply(p, dp=dp)
+    ybf = gpu_apply(p, prec=b.MIXED_BF16, dp=dp)
+    e = rel(ybf, y64)
+    print(f"C5 bf16 relative error {e:.3e}", flush=True)
+    assert e < 2e-2

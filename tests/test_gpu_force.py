@@ -96,3 +96,11 @@ def test_rejects_bad_arguments():
     with pytest.raises(b.AbacusPwError) as e:
         b.force_nl(dp, x, np.ones(p.nb + 3))
     assert e.value.name == "EBAD_SHAPE"
+
+
+def test_no_projectors_gives_zero_force():
+    p = W.make_problem(W.tiny_config(fft=8, ecut=6.0, nb=2, natom=2))
+    q = dataclasses.replace(p, nproj=0, beta=np.zeros(0, dtype=np.complex128), dmat=np.zeros(0),
+                            proj_atom_offset=np.zeros(p.natom + 1, dtype=np.int32))
+    f = gpu_force(q, np.ones((q.nk, q.nb)))
+    assert f.shape == (q.natom, 3) and np.all(f == 0.0)
