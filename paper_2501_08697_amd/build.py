@@ -36,7 +36,7 @@ COMMON = ["-O3", "-std=c++17", "-fPIC", f"-I{os.path.join(ROOT, 'include')}", f"
 SCRATCH_ALLOWED = {
     # full-plane y-z forward pass at 120 and 128 in FP64: never launched (the plane
     # exceeds LDS at FP64, the compact-row kernel runs instead)
-    "_ZN3apw8k_yz_fwdILi120EddE": 64,
+    "_ZN3apw8k_yz_fwdILi120EddE": 128,
     "_ZN3apw8k_yz_fwdILi128EddE": 256,
     # tridiagonal reduction with its panel in global memory (subspace above 256): 8 bytes
     "_ZN3apw7k_hetrdILb0EE": 16,

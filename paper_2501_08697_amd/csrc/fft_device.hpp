@@ -64,8 +64,8 @@ APW_LDS_SPLIT(90, 9, 10)
 APW_LDS_SPLIT(96, 8, 12)
 APW_LDS_SPLIT(100, 10, 10)
 APW_LDS_SPLIT(108, 9, 12)
-APW_LDS_SPLIT(120, 8, 15)
-APW_LDS_SPLIT(128, 8, 16)
+APW_LDS_SPLIT(120, 15, 8)
+APW_LDS_SPLIT(128, 16, 8)
 #undef APW_LDS_SPLIT
 
 // ------------------------------------------------------------ codelets ----

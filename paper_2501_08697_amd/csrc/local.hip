@@ -146,8 +146,8 @@ __global__ __launch_bounds__((yz_threads<N, T>())) void k_yz_inv(const cx<TIN> *
 //      belong to the slab go straight to HBM.
 // So each element crosses LDS twice per band (once per transpose) and there
 // are three barriers per band. The next band's phase-I values are fetched as
-// soon as phase I has consumed the current ones, behind phases F and O. The tile width keeps w3 B <= 256, so every
-// thread owns at most one task per phase.
+// soon as phase I has consumed the current ones, behind phases F and O. The tile width keeps w3 max(A, B) <= 256,
+// so every thread owns at most one task per phase.
 template <int N1, typename T, typename TV>
 __global__ __launch_bounds__(256) void k_xpass(cx<T> *__restrict__ slab, int nslab, int N2, int N3, int T3, int nt3,
                                                int nbands, int bpw, const int *__restrict__ row_to_slab,
@@ -718,12 +718,12 @@ static int launch_yz(bool inverse, const Plan &P, int k0, int nkb, const BatchAr
     return check_launch("yz_fwd");
 }
 
-// j3 tile width of the x pass: the widest divisor of N3 that keeps T3 * B <= 256
+// j3 tile width of the x pass: the widest divisor of N3 that keeps T3 * max(A, B) <= 256
 // (one task per thread and phase) and T3 <= 32; else that bound with a ragged tile.
 static int xpass_tile(int n1, int n3) {
     int a, b;
     lds_split_host(n1, &a, &b);
-    const int cap = std::min(kMaxT3, 256 / b);
+    const int cap = std::min(kMaxT3, 256 / std::max(a, b));   // one task per thread in both phases
     for (int t = cap; t >= 4; --t)
         if (n3 % t == 0) return t;
     return std::min(cap, n3);
