@@ -4,7 +4,10 @@
  * The library applies the Kohn-Sham Hamiltonian of the plane-wave method
  * (Sec. III.A, the KS equation written in the plane-wave basis) to blocks of
  * bands, and solves for its lowest eigenpairs with a block Davidson method
- * (Sec. III.B names Davidson as the iterative eigensolver). The potential is
+ * (Sec. III.B names Davidson as the iterative eigensolver) or band-by-band CG
+ * (the CG figure of Sec. III.B). Around that it provides the adjoint of H psi,
+ * the band density, the Chebyshev-filtered application of Sec. III.C and the
+ * nonlocal force of Sec. III.A. The potential is
  * the norm-conserving split of Sec. II.A ("Pseudopotentials"): a local part
  * sampled on the real-space FFT grid plus the Kleinman-Bylander separable
  * nonlocal part sum_ij |beta_i> D_ij <beta_j|.
