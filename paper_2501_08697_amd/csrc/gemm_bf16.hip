@@ -72,12 +72,13 @@ __device__ __forceinline__ void split16(const u4 g[4], u4 re[2], u4 im[2]) {
 template <bool kConj, bool kIntoF64>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_bf16_t128(int M, int N, int Kp, int kchunk, const uint32_t *__restrict__ A,
                                                    int64_t lda, const uint32_t *__restrict__ B, int64_t ldb,
-                                                   void *__restrict__ out, int64_t ldo) {
+                                                   void *__restrict__ out, int64_t ldo, int b_fastest) {
     __shared__ __align__(16) uint32_t Are[T2 * P2], Aim[T2 * P2], Bre[T2 * P2], Bim[T2 * P2];
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     int bx, by, bz;
     xcd_block(bx, by, bz);
-    const int i0 = bx * T2, j0 = by * T2, s = bz;
+    // b_fastest: the grid's x runs over B tiles, so the blocks that share an A tile run together
+    const int i0 = (b_fastest ? by : bx) * T2, j0 = (b_fastest ? bx : by) * T2, s = bz;
     const int kb = s * kchunk, ke = min(Kp, kb + kchunk);
     // loader: row tid / 2 of each tile, k half (tid % 2) * 16 of the stage
     const int lr = tid >> 1, lh = (tid & 1) * 16;
@@ -244,7 +245,7 @@ int proj_dapply_bf16(int M, int N, int K, const void *Bpk, int64_t ldb, const vo
         KernelTimer kt("gemm_cn_bf16", st);
         hipLaunchKernelGGL((k_bf16_t128<true, false>), grid, dim3(256), 0, st, M, N, Kp, c,
                            static_cast<const uint32_t *>(Bpk), ldb, static_cast<const uint32_t *>(psi_pk), ldp, part,
-                           (int64_t)0);
+                           (int64_t)0, 0);
         APW_TRY(check_launch("gemm_cn_bf16"));
     }
     return reduce_dapply_f32(M, N, ns, part, dmat, blo, bn, bdoff, Q, st);
@@ -272,7 +273,7 @@ int gemm_cn_bf16_of_f64(int M, int N, int K, const void *A, int64_t lda, const v
     {
         KernelTimer kt("gemm_cn_bf16", st);
         hipLaunchKernelGGL((k_bf16_t128<true, false>), grid, dim3(256), 0, st, M, N, Kp, c, apk, (int64_t)Kp, bpk,
-                           (int64_t)Kp, part, (int64_t)0);
+                           (int64_t)Kp, part, (int64_t)0, 0);
         APW_TRY(check_launch("gemm_cn_bf16"));
     }
     return reduce_parts_f32_to_f64(M, N, ns, part, C, ldc, 1.0, 0.0, st);
@@ -282,10 +283,12 @@ int gemm_nn_bf16_into_f64(int N, int G, int K, const void *Apk, int64_t lda, con
                           int64_t ldc, hipStream_t st) {
     if (N <= 0 || G <= 0) return ABACUS_PW_OK;
     const int Kp = bf16_ld(K);
-    dim3 grid(ceil_div(G, T2), ceil_div(N, T2), 1);
+    // band tiles fastest: the blocks that read one tile of the transposed beta run together, so
+    // beta streams from HBM once while the small Q is re-read from cache
+    dim3 grid(ceil_div(N, T2), ceil_div(G, T2), 1);
     KernelTimer kt("gemm_nn_bf16", st);
     hipLaunchKernelGGL((k_bf16_t128<false, true>), grid, dim3(256), 0, st, G, N, Kp, Kp,
-                       static_cast<const uint32_t *>(BTpk), ldbt, static_cast<const uint32_t *>(Apk), lda, C, ldc);
+                       static_cast<const uint32_t *>(BTpk), ldbt, static_cast<const uint32_t *>(Apk), lda, C, ldc, 1);
     return check_launch("gemm_nn_bf16");
 }
 
