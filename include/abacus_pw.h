@@ -44,6 +44,14 @@
  * for a geometry builds the plan (it allocates and synchronises), later calls
  * only enqueue kernels.
  *
+ * Threads: the plan cache is shared and locked; a plan evicted by one thread
+ * stays alive until every call that holds it has returned, and its device
+ * buffers are freed only after the device is idle. Calls that share a plan
+ * (same geometry) share its work space: they must be issued on one stream, or
+ * the caller must order them (events, synchronisation). Calls on different
+ * plans are independent. The tuning knobs (abacus_pw_set_tuning) are
+ * process-wide.
+ *
  * Errors: every entry point returns 0 on success and a negative ABACUS_PW_E*
  * code on failure (nothing has been enqueued when a validation error is
  * returned); abacus_pw_last_error() gives a message for the calling thread.
@@ -93,8 +101,8 @@ extern "C" {
  * nk, kpts         host [nk][3] cartesian k-points (bohr^-1).
  * npw              host [nk] sphere sizes.
  * miller           host [sum npw][3] int32 Miller triples, k-major (the G-sphere index map).
- *                  Keyed by pointer in the plan cache: after editing it in place call
- *                  abacus_pw_plan_reset().
+ *                  The plan cache keys on the pointer and a hash of every triple, so a map
+ *                  edited in place gets a new plan.
  * vloc             device [N1][N2][N3] float64 local potential V_loc(r_j) (Ry).
  * nproj            projectors per k-point (same count and order at every k).
  * natom            number of atom blocks.
@@ -104,7 +112,12 @@ extern "C" {
  *                  blocks back to back.
  * flags            ABACUS_PW_STATIC_OPERATOR or 0.
  *
- * V_loc and D are checked (finite; D symmetric) when a plan is first built.
+ * V_loc and D are checked (finite; D symmetric) once per plan, when the plan is
+ * first built, by copies enqueued on the caller's stream (so they see the
+ * caller's earlier writes). Later calls with the same geometry reuse the plan
+ * and do not re-check: a caller that changes V or D between calls (an SCF
+ * update, a finite-difference step) is responsible for their finiteness and
+ * for the symmetry of D.
  */
 typedef struct abacus_pw_problem {
     double lattice[9];

@@ -66,6 +66,7 @@ def lib():
         _lib.oracle_apply_h_backward.argtypes = [P, i, vp, vp, vp, vp, vp]
         _lib.oracle_density.argtypes = [P, i, vp, vp, vp]
         _lib.oracle_num_threads.restype = i
+        _lib.oracle_set_num_threads.argtypes = [i]
     return _lib
 
 
@@ -97,6 +98,11 @@ class _Bound:
 
 def num_threads() -> int:
     return int(lib().oracle_num_threads())
+
+
+def set_num_threads(n: int) -> None:
+    """OpenMP threads for later oracle calls."""
+    lib().oracle_set_num_threads(int(n))
 
 
 def dft1d(x: np.ndarray, sign: int) -> np.ndarray:

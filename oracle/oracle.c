@@ -490,3 +490,6 @@ void oracle_density(const oracle_problem *p, int nb, const cplx *psi, const doub
 }
 
 int oracle_num_threads(void) { return omp_get_max_threads(); }
+
+/* Sets the OpenMP thread count of later calls (the CPU baseline times 1 thread and all threads). */
+void oracle_set_num_threads(int n) { omp_set_num_threads(n > 0 ? n : 1); }

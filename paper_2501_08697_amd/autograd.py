@@ -17,6 +17,7 @@ from . import binding
 class PwApplyH(torch.autograd.Function):
     @staticmethod
     def forward(ctx, psi, vloc, dmat, dp, precision):
+        psi, vloc, dmat = psi.contiguous(), vloc.contiguous(), dmat.contiguous()
         y = binding.apply_h(dp, psi, precision, vloc=vloc, dmat=dmat)
         ctx.save_for_backward(psi, vloc, dmat)
         ctx.dp = dp

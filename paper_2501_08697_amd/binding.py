@@ -86,6 +86,42 @@ def check(code: int) -> int:
     return code
 
 
+def _dev_tensor(t, name: str, dtype, numel: int, device=None):
+    """Checks a tensor argument before its pointer crosses the C ABI: a CUDA
+    (HIP) tensor of the given dtype, contiguous, with exactly numel elements, on
+    the expected device. Raises AbacusPwError(EBAD_SHAPE) otherwise; nothing is
+    copied or converted (a silent copy of an in/out buffer would drop the update)."""
+    import torch
+    if not isinstance(t, torch.Tensor):
+        raise AbacusPwError(-2, f"{name} must be a torch tensor")
+    if not t.is_cuda:
+        raise AbacusPwError(-2, f"{name} must be a device tensor (got {t.device})")
+    if device is not None and t.device != device:
+        raise AbacusPwError(-2, f"{name} is on {t.device}, expected {device}")
+    if t.dtype != dtype:
+        raise AbacusPwError(-2, f"{name} must be {dtype} (got {t.dtype})")
+    if not t.is_contiguous():
+        raise AbacusPwError(-2, f"{name} must be contiguous")
+    if t.numel() != numel:
+        raise AbacusPwError(-2, f"{name} must hold {numel} elements (got {t.numel()})")
+    return t
+
+
+def _psi_dtype(precision: int):
+    import torch
+    if precision not in (FP64, FP32, MIXED_BF16, MIXED_FP32):
+        raise AbacusPwError(-7, f"unknown precision {precision}")
+    return torch.complex64 if precision == FP32 else torch.complex128
+
+
+def _weights(dp, occ, nb, device):
+    import torch
+    w = torch.as_tensor(occ, dtype=torch.float64).to(device).contiguous()
+    if w.numel() != dp.nk * nb:
+        raise AbacusPwError(-2, f"occ must hold nk * nb = {dp.nk * nb} weights, got {w.numel()}")
+    return w
+
+
 def _stream(stream=None) -> int:
     import torch
     s = torch.cuda.current_stream() if stream is None else stream
@@ -142,16 +178,30 @@ class DeviceProblem:
     def psi_len(self, nb: int) -> int:
         return nb * int(self.pw_off[-1])
 
+    def check_operator(self, device, vloc=None, dmat=None):
+        """The operator tensors passed to the library: vloc float64 [N1 N2 N3], beta complex128
+        [nproj sum npw], dmat float64 (the concatenated atom blocks), all contiguous on `device`."""
+        import torch
+        n = self.fft[0] * self.fft[1] * self.fft[2]
+        _dev_tensor(self.vloc if vloc is None else vloc, "vloc", torch.float64, n, device)
+        if self.nproj > 0:
+            offs = self._offs.astype(np.int64)
+            dlen = int(np.sum((offs[1:] - offs[:-1]) ** 2))
+            _dev_tensor(self.beta, "beta", torch.complex128, self.nproj * int(self.pw_off[-1]), device)
+            _dev_tensor(self.dmat if dmat is None else dmat, "dmat", torch.float64, dlen, device)
+
 
 def apply_h(dp: DeviceProblem, psi, precision: int = FP64, nb: int | None = None, out=None, stream=None,
             vloc=None, dmat=None):
     """H psi for a packed psi tensor (complex128, or complex64 for FP32)."""
     import torch
     nb = dp.prob.nb if nb is None else nb
-    if psi.numel() != dp.psi_len(nb):
-        raise ValueError("psi has the wrong length for nb bands")
-    psi = psi.contiguous()
-    y = torch.empty_like(psi) if out is None else out
+    dt = _psi_dtype(precision)
+    _dev_tensor(psi, "psi", dt, dp.psi_len(nb))
+    y = torch.empty_like(psi) if out is None else _dev_tensor(out, "out", dt, dp.psi_len(nb), psi.device)
+    if y.data_ptr() == psi.data_ptr():
+        raise AbacusPwError(-2, "out must not alias psi")
+    dp.check_operator(psi.device, vloc, dmat)
     cp = dp.c(vloc, dmat)
     check(lib().abacus_pw_apply_h(C.byref(cp), int(precision), int(nb), psi.data_ptr(), y.data_ptr(),
                                   _stream(stream)))
@@ -163,7 +213,12 @@ def apply_h_backward(dp: DeviceProblem, psi, dy, precision: int = FP64, nb: int 
     """(grad_psi, grad_vloc, grad_dmat) of L with upstream dy = dL/d(H psi)."""
     import torch
     nb = dp.prob.nb if nb is None else nb
-    psi, dy = psi.contiguous(), dy.contiguous()
+    if precision not in (FP64, FP32):
+        raise AbacusPwError(-7, "the adjoint runs in FP64 or FP32")
+    dt = _psi_dtype(precision)
+    _dev_tensor(psi, "psi", dt, dp.psi_len(nb))
+    _dev_tensor(dy, "dy", dt, dp.psi_len(nb), psi.device)
+    dp.check_operator(psi.device, vloc, dmat)
     gp = torch.empty_like(psi) if "psi" in want else None
     gv = torch.empty(dp.fft, dtype=torch.float64, device=psi.device) if "v" in want else None
     gd = torch.empty_like(dp.dmat) if "d" in want else None
@@ -179,11 +234,14 @@ def density(dp: DeviceProblem, psi, occ, precision: int = FP64, nb: int | None =
     """rho [N1][N2][N3] float64 = sum_{k,n} occ[k][n] |psi_nk(r)|^2 (occ: [nk][nb], numpy or torch)."""
     import torch
     nb = dp.prob.nb if nb is None else nb
-    psi = psi.contiguous()
-    w = torch.as_tensor(occ, dtype=torch.float64).to(psi.device).contiguous()
-    if w.numel() != dp.nk * nb:
-        raise AbacusPwError(-2, f"occ must hold nk * nb = {dp.nk * nb} weights, got {w.numel()}")
-    rho = torch.empty(dp.fft, dtype=torch.float64, device=psi.device) if out is None else out
+    if precision not in (FP64, FP32):
+        raise AbacusPwError(-7, "the density runs in FP64 or FP32")
+    _dev_tensor(psi, "psi", _psi_dtype(precision), dp.psi_len(nb))
+    dp.check_operator(psi.device)
+    w = _weights(dp, occ, nb, psi.device)
+    n = dp.fft[0] * dp.fft[1] * dp.fft[2]
+    rho = (torch.empty(dp.fft, dtype=torch.float64, device=psi.device) if out is None
+           else _dev_tensor(out, "out", torch.float64, n, psi.device))
     cp = dp.c()
     check(lib().abacus_pw_density(C.byref(cp), int(precision), int(nb), psi.data_ptr(), w.data_ptr(), rho.data_ptr(),
                                   _stream(stream)))
@@ -194,10 +252,9 @@ def force_nl(dp: DeviceProblem, psi, occ, nb: int | None = None, stream=None):
     """Nonlocal force [natom][3] (Ry/bohr, device float64) for band weights occ [nk][nb]."""
     import torch
     nb = dp.prob.nb if nb is None else nb
-    psi = psi.contiguous()
-    w = torch.as_tensor(occ, dtype=torch.float64).to(psi.device).contiguous()
-    if w.numel() != dp.nk * nb:
-        raise AbacusPwError(-2, f"occ must hold nk * nb = {dp.nk * nb} weights, got {w.numel()}")
+    _dev_tensor(psi, "psi", torch.complex128, dp.psi_len(nb))
+    dp.check_operator(psi.device)
+    w = _weights(dp, occ, nb, psi.device)
     f = torch.empty((dp.natom, 3), dtype=torch.float64, device=psi.device)
     cp = dp.c()
     check(lib().abacus_pw_force_nl(C.byref(cp), FP64, int(nb), psi.data_ptr(), w.data_ptr(), f.data_ptr(),
@@ -210,11 +267,15 @@ def chebyshev(dp: DeviceProblem, chi, coef, emin, emax, precision: int = FP64, n
     """sum_n coef[n] T_n((H - c)/h) chi, c and h the centre and half width of [emin, emax]."""
     import torch
     nb = dp.prob.nb if nb is None else nb
-    chi = chi.contiguous()
+    dt = _psi_dtype(precision)
+    _dev_tensor(chi, "chi", dt, dp.psi_len(nb))
     cf = np.ascontiguousarray(coef, dtype=np.float64).reshape(-1)
     if cf.size < 1:
         raise AbacusPwError(-2, "need at least one coefficient")
-    y = torch.empty_like(chi) if out is None else out
+    y = torch.empty_like(chi) if out is None else _dev_tensor(out, "out", dt, dp.psi_len(nb), chi.device)
+    if y.data_ptr() == chi.data_ptr():
+        raise AbacusPwError(-2, "out must not alias chi")
+    dp.check_operator(chi.device)
     cp = dp.c()
     check(lib().abacus_pw_chebyshev(C.byref(cp), int(precision), int(nb), chi.data_ptr(), y.data_ptr(),
                                     cf.ctypes.data, int(cf.size - 1), float(emin), float(emax), _stream(stream)))
@@ -232,7 +293,10 @@ def fermi_coefficients(order: int, emin: float, emax: float, mu: float, kt: floa
 def davidson(dp: DeviceProblem, psi, tol=1e-8, max_iter=100, ndim=2, precision: int = FP64, nb: int | None = None,
              stream=None):
     """Block Davidson; psi (complex128) is updated in place. Returns (eig, resid, iters, status)."""
+    import torch
     nb = dp.prob.nb if nb is None else nb
+    _dev_tensor(psi, "psi", torch.complex128, dp.psi_len(nb))
+    dp.check_operator(psi.device)
     eig = np.zeros((dp.nk, nb))
     res = np.zeros((dp.nk, nb))
     its = np.zeros(dp.nk, dtype=np.int32)
@@ -246,7 +310,10 @@ def davidson(dp: DeviceProblem, psi, tol=1e-8, max_iter=100, ndim=2, precision: 
 def cg(dp: DeviceProblem, psi, tol=1e-8, max_iter=200, nb: int | None = None, stream=None):
     """Band-by-band preconditioned CG; psi (complex128) is updated in place.
     Returns (eig [nk][nb], resid [nk][nb], steps [nk][nb], status)."""
+    import torch
     nb = dp.prob.nb if nb is None else nb
+    _dev_tensor(psi, "psi", torch.complex128, dp.psi_len(nb))
+    dp.check_operator(psi.device)
     eig = np.zeros((dp.nk, nb))
     res = np.zeros((dp.nk, nb))
     its = np.zeros((dp.nk, nb), dtype=np.int32)

@@ -161,8 +161,8 @@ int abacus_pw_apply_h(const abacus_pw_problem *p, int precision, int nb, const v
         if (psi == hpsi) return set_error(ABACUS_PW_EBAD_SHAPE, "hpsi must not alias psi");
         if (nb < 1) return set_error(ABACUS_PW_EBAD_SHAPE, "nb must be >= 1");
         if (precision < 0 || precision > 3) return set_error(ABACUS_PW_EBAD_PRECISION, "unknown precision");
-        Plan *P = nullptr;
-        APW_TRY(get_plan(p, &P));
+        std::shared_ptr<Plan> P;
+        APW_TRY(get_plan(p, static_cast<hipStream_t>(stream), P));
         return apply_h_all(*p, *P, precision, nb, psi, hpsi, static_cast<hipStream_t>(stream));
     });
 }
@@ -174,8 +174,8 @@ int abacus_pw_apply_h_backward(const abacus_pw_problem *p, int precision, int nb
         if (nb < 1) return set_error(ABACUS_PW_EBAD_SHAPE, "nb must be >= 1");
         if (precision != ABACUS_PW_FP64 && precision != ABACUS_PW_FP32)
             return set_error(ABACUS_PW_EBAD_PRECISION, "the adjoint runs in FP64 or FP32");
-        Plan *P = nullptr;
-        APW_TRY(get_plan(p, &P));
+        std::shared_ptr<Plan> P;
+        APW_TRY(get_plan(p, static_cast<hipStream_t>(stream), P));
         return apply_h_backward_all(*p, *P, precision, nb, psi, dY, grad_psi, grad_vloc, grad_dmat,
                                     static_cast<hipStream_t>(stream));
     });
@@ -188,8 +188,8 @@ int abacus_pw_density(const abacus_pw_problem *p, int precision, int nb, const v
         if (nb < 1) return set_error(ABACUS_PW_EBAD_SHAPE, "nb must be >= 1");
         if (precision != ABACUS_PW_FP64 && precision != ABACUS_PW_FP32)
             return set_error(ABACUS_PW_EBAD_PRECISION, "the density runs in FP64 or FP32");
-        Plan *P = nullptr;
-        APW_TRY(get_plan(p, &P));
+        std::shared_ptr<Plan> P;
+        APW_TRY(get_plan(p, static_cast<hipStream_t>(stream), P));
         return density_all(*p, *P, precision, nb, psi, occ, rho, static_cast<hipStream_t>(stream));
     });
 }
@@ -200,8 +200,8 @@ int abacus_pw_force_nl(const abacus_pw_problem *p, int precision, int nb, const 
         if (!psi || !occ || !force) return set_error(ABACUS_PW_ENULL_ARG, "psi, occ and force are required");
         if (nb < 1) return set_error(ABACUS_PW_EBAD_SHAPE, "nb must be >= 1");
         if (precision != ABACUS_PW_FP64) return set_error(ABACUS_PW_EBAD_PRECISION, "the force runs in FP64");
-        Plan *P = nullptr;
-        APW_TRY(get_plan(p, &P));
+        std::shared_ptr<Plan> P;
+        APW_TRY(get_plan(p, static_cast<hipStream_t>(stream), P));
         return force_nl_all(*p, *P, nb, psi, occ, force, static_cast<hipStream_t>(stream));
     });
 }
@@ -217,8 +217,8 @@ int abacus_pw_chebyshev(const abacus_pw_problem *p, int precision, int nb, const
         for (int i = 0; i <= order; ++i)
             if (!std::isfinite(coef[i])) return set_error(ABACUS_PW_ENONFINITE, "coefficient is not finite");
         if (precision < 0 || precision > 3) return set_error(ABACUS_PW_EBAD_PRECISION, "unknown precision");
-        Plan *P = nullptr;
-        APW_TRY(get_plan(p, &P));
+        std::shared_ptr<Plan> P;
+        APW_TRY(get_plan(p, static_cast<hipStream_t>(stream), P));
         return chebyshev_all(*p, *P, precision, nb, chi, out, coef, order, emin, emax,
                              static_cast<hipStream_t>(stream));
     });
@@ -245,8 +245,8 @@ int abacus_pw_davidson(const abacus_pw_problem *p, int precision, int nb, void *
         if (!(tol > 0.0)) return set_error(ABACUS_PW_EBAD_SHAPE, "tol must be > 0");
         if (precision != ABACUS_PW_FP64 && precision != ABACUS_PW_MIXED_FP32 && precision != ABACUS_PW_MIXED_BF16)
             return set_error(ABACUS_PW_EBAD_PRECISION, "Davidson runs in FP64 or a MIXED mode");
-        Plan *P = nullptr;
-        APW_TRY(get_plan(p, &P));
+        std::shared_ptr<Plan> P;
+        APW_TRY(get_plan(p, static_cast<hipStream_t>(stream), P));
         for (int k = 0; k < p->nk; ++k)
             if (p->npw[k] < nb) return set_error(ABACUS_PW_EBAD_SHAPE, "nb exceeds the sphere size");
         return davidson_all(*p, *P, precision, nb, psi_inout, eig, tol, max_iter, ndim, iters, resid,
@@ -260,8 +260,8 @@ int abacus_pw_cg(const abacus_pw_problem *p, int nb, void *psi_inout, double *ei
         if (!psi_inout || !eig) return set_error(ABACUS_PW_ENULL_ARG, "psi_inout and eig are required");
         if (nb < 1 || max_iter < 0) return set_error(ABACUS_PW_EBAD_SHAPE, "need nb >= 1, max_iter >= 0");
         if (!(tol > 0.0)) return set_error(ABACUS_PW_EBAD_SHAPE, "tol must be > 0");
-        Plan *P = nullptr;
-        APW_TRY(get_plan(p, &P));
+        std::shared_ptr<Plan> P;
+        APW_TRY(get_plan(p, static_cast<hipStream_t>(stream), P));
         for (int k = 0; k < p->nk; ++k)
             if (p->npw[k] < nb) return set_error(ABACUS_PW_EBAD_SHAPE, "nb exceeds the sphere size");
         return cg_all(*p, *P, nb, psi_inout, eig, tol, max_iter, iters, resid, static_cast<hipStream_t>(stream));

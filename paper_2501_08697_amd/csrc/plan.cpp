@@ -28,6 +28,10 @@ DeviceBuffer::~DeviceBuffer() {
     if (ptr) (void)hipFree(ptr);
 }
 
+// Kernels enqueued by an earlier call may still read the plan's tables and work
+// space; its buffers are released only after the device has drained them.
+Plan::~Plan() { (void)hipDeviceSynchronize(); }
+
 int DeviceBuffer::ensure(size_t n) {
     if (n <= bytes && ptr) return ABACUS_PW_OK;
     if (ptr) {
@@ -80,36 +84,32 @@ struct Key {
     std::vector<double> kpts;
     std::vector<int> npw;
     const int *miller;
-    uint64_t miller_sample;
+    uint64_t miller_hash;
     int nproj, natom;
     std::vector<int> offs;
     int device;
     bool operator==(const Key &o) const {
         return std::memcmp(lattice, o.lattice, sizeof lattice) == 0 && std::memcmp(fft, o.fft, sizeof fft) == 0 &&
                ecut == o.ecut && nk == o.nk && kpts == o.kpts && npw == o.npw && miller == o.miller &&
-               miller_sample == o.miller_sample && nproj == o.nproj && natom == o.natom && offs == o.offs &&
+               miller_hash == o.miller_hash && nproj == o.nproj && natom == o.natom && offs == o.offs &&
                device == o.device;
     }
 };
 
-// FNV-1a over at most 4096 evenly spaced Miller triples plus the first and last ones.
-uint64_t sample_hash(const int *m, int64_t n) {
+// FNV-1a over every Miller triple (about 1 ms per million triples): a caller
+// that reorders or edits the map in the same buffer gets a new plan.
+uint64_t miller_fnv(const int *m, int64_t n) {
     uint64_t h = 1469598103934665603ull;
-    auto mix = [&](int64_t i) {
-        for (int c = 0; c < 3; ++c) {
-            h ^= (uint32_t)m[3 * i + c];
-            h *= 1099511628211ull;
-        }
-    };
-    const int64_t step = std::max<int64_t>(1, n / 4096);
-    for (int64_t i = 0; i < n; i += step) mix(i);
-    if (n > 0) mix(n - 1);
+    for (int64_t i = 0; i < 3 * n; ++i) {
+        h ^= (uint32_t)m[i];
+        h *= 1099511628211ull;
+    }
     return h;
 }
 
 struct Entry {
     Key key;
-    std::unique_ptr<Plan> plan;
+    std::shared_ptr<Plan> plan;
     uint64_t last_use;
 };
 
@@ -129,7 +129,7 @@ Key make_key(const abacus_pw_problem *p) {
     int64_t tot = 0;
     for (int i = 0; i < p->nk; ++i) tot += p->npw[i];
     k.miller = p->miller;
-    k.miller_sample = sample_hash(p->miller, tot);
+    k.miller_hash = miller_fnv(p->miller, tot);
     k.nproj = p->nproj;
     k.natom = p->natom;
     if (p->nproj > 0) k.offs.assign(p->proj_atom_offset, p->proj_atom_offset + p->natom + 1);
@@ -158,7 +158,7 @@ int perm_slot_host(int k, int n) {
     return b * (k % a) + k / a;
 }
 
-int build_plan(const abacus_pw_problem *p, Plan &P) {
+int build_plan(const abacus_pw_problem *p, Plan &P, hipStream_t st) {
     std::memcpy(P.lattice, p->lattice, sizeof P.lattice);
     P.N1 = p->fft[0];
     P.N2 = p->fft[1];
@@ -344,16 +344,20 @@ int build_plan(const abacus_pw_problem *p, Plan &P) {
     P.proj_blk_n = reinterpret_cast<const int *>(at(o_bn));
     P.proj_blk_doff = reinterpret_cast<const int *>(at(o_bdoff));
 
-    // operator data checks (once per plan): V finite, D finite and symmetric
+    // operator data checks (once per plan): V finite, D finite and symmetric. The
+    // copies run on the caller's stream, behind whatever it has enqueued that
+    // writes V or D.
     {
         std::vector<double> v((size_t)P.N);
-        APW_HIP(hipMemcpy(v.data(), p->vloc, sizeof(double) * (size_t)P.N, hipMemcpyDeviceToHost));
+        APW_HIP(hipMemcpyAsync(v.data(), p->vloc, sizeof(double) * (size_t)P.N, hipMemcpyDeviceToHost, st));
+        APW_HIP(hipStreamSynchronize(st));
         for (double x : v)
             if (!std::isfinite(x)) return set_error(ABACUS_PW_ENONFINITE, "V_loc has a NaN or Inf");
     }
     if (p->nproj > 0) {
         std::vector<double> d((size_t)P.dmat_len);
-        APW_HIP(hipMemcpy(d.data(), p->dmat, sizeof(double) * (size_t)P.dmat_len, hipMemcpyDeviceToHost));
+        APW_HIP(hipMemcpyAsync(d.data(), p->dmat, sizeof(double) * (size_t)P.dmat_len, hipMemcpyDeviceToHost, st));
+        APW_HIP(hipStreamSynchronize(st));
         int64_t o = 0;
         for (int at2 = 0; at2 < p->natom; ++at2) {
             const int n = p->proj_atom_offset[at2 + 1] - p->proj_atom_offset[at2];
@@ -374,26 +378,40 @@ int build_plan(const abacus_pw_problem *p, Plan &P) {
 
 }  // namespace
 
-int get_plan(const abacus_pw_problem *p, Plan **out) {
+int get_plan(const abacus_pw_problem *p, hipStream_t st, std::shared_ptr<Plan> &out) {
     APW_TRY(validate_problem_shallow(p));
     Key key = make_key(p);
     std::lock_guard<std::mutex> lock(g_mu);
     for (auto &e : g_cache)
         if (e.key == key) {
             e.last_use = ++g_clock;
-            *out = e.plan.get();
+            out = e.plan;
             return ABACUS_PW_OK;
         }
-    auto plan = std::make_unique<Plan>();
-    APW_TRY(build_plan(p, *plan));
+    auto plan = std::make_shared<Plan>();
+    APW_TRY(build_plan(p, *plan, st));
     if (g_cache.size() >= kMaxPlans) {
+        // an evicted plan lives on while a caller still holds it
         auto it = std::min_element(g_cache.begin(), g_cache.end(),
                                    [](const Entry &a, const Entry &b) { return a.last_use < b.last_use; });
-        APW_HIP(hipDeviceSynchronize());
         g_cache.erase(it);
     }
-    g_cache.push_back(Entry{std::move(key), std::move(plan), ++g_clock});
-    *out = g_cache.back().plan.get();
+    g_cache.push_back(Entry{std::move(key), plan, ++g_clock});
+    out = std::move(plan);
+    return ABACUS_PW_OK;
+}
+
+int find_plan(const abacus_pw_problem *p, std::shared_ptr<Plan> &out) {
+    APW_TRY(validate_problem_shallow(p));
+    Key key = make_key(p);
+    std::lock_guard<std::mutex> lock(g_mu);
+    for (auto &e : g_cache)
+        if (e.key == key) {
+            e.last_use = ++g_clock;
+            out = e.plan;
+            return ABACUS_PW_OK;
+        }
+    out.reset();
     return ABACUS_PW_OK;
 }
 

@@ -4,6 +4,7 @@
 #pragma once
 
 #include <cstdint>
+#include <memory>
 #include <vector>
 
 #include "common.hpp"
@@ -53,6 +54,7 @@ struct DeviceBuffer {
 };
 
 struct Plan {
+    ~Plan();   // waits for the device before its buffers are freed
     // geometry
     double lattice[9];
     double recip[9];
@@ -116,8 +118,11 @@ extern int g_x_bands;       // bands per x-pass work-group
 extern int g_yz_mode;       // plane kernels: 0 auto, 1 full plane in LDS, 2 compact rows
 extern int g_overlap;       // projector GEMMs beside the local term: 0 default (off), 1 on, 2 off
 
-// Looks up or builds the plan for a problem (validates it on build).
-int get_plan(const abacus_pw_problem *p, Plan **out);
+// Looks up or builds the plan for a problem (validates it on build; the
+// operator checks read V and D on `st`, after the caller's earlier work on it).
+// The caller holds the returned reference for the duration of its call, so a
+// plan evicted by another thread meanwhile stays alive until then.
+int get_plan(const abacus_pw_problem *p, hipStream_t st, std::shared_ptr<Plan> &out);
 
 // Host-side checks of a problem that do not need a plan.
 int validate_problem_shallow(const abacus_pw_problem *p);

@@ -188,3 +188,32 @@ def test_force_rejects_before_device_access(prob):
     assert code_name(lib.abacus_pw_force_nl(C.byref(f.s), 0, 1, FAKE, FAKE, None, None)) == "ENULL_ARG"
     assert code_name(lib.abacus_pw_force_nl(C.byref(f.s), 0, 0, FAKE, FAKE, FAKE, None)) == "EBAD_SHAPE"
     assert code_name(lib.abacus_pw_force_nl(C.byref(f.s), 1, 1, FAKE, FAKE, FAKE, None)) == "EBAD_PRECISION"
+
+
+def test_binding_checks_tensors_before_the_library(prob):
+    """Every binding entry point refuses host tensors, wrong dtypes, wrong lengths and
+    non-contiguous views before a pointer reaches the C ABI (here no GPU exists, so a
+    pointer that got through would fail differently)."""
+    import torch
+    dp = B.DeviceProblem(prob, device="cpu")
+    n = dp.psi_len(prob.nb)
+    psi = torch.zeros(n, dtype=torch.complex128)
+    calls = {
+        "apply_h": lambda x: B.apply_h(dp, x),
+        "apply_h_fp32": lambda x: B.apply_h(dp, x, B.FP32),
+        "apply_h_backward": lambda x: B.apply_h_backward(dp, x, x),
+        "density": lambda x: B.density(dp, x, np.ones((dp.nk, prob.nb))),
+        "force_nl": lambda x: B.force_nl(dp, x, np.ones((dp.nk, prob.nb))),
+        "chebyshev": lambda x: B.chebyshev(dp, x, [1.0, 0.5], -1.0, 1.0),
+        "davidson": lambda x: B.davidson(dp, x),
+        "cg": lambda x: B.cg(dp, x),
+    }
+    for name, call in calls.items():
+        for bad in (psi, psi[:-1], psi.to(torch.complex64) if name != "apply_h_fp32" else psi,
+                    torch.zeros(2 * n, dtype=torch.complex128)[::2]):
+            with pytest.raises(B.AbacusPwError) as e:
+                call(bad)
+            assert e.value.code == -2, (name, str(e.value))
+    with pytest.raises(B.AbacusPwError) as e:
+        B.apply_h(dp, psi, precision=7)
+    assert e.value.code == -7
