@@ -183,6 +183,22 @@ def density(prob, psi, occ, nb=None):
     return rho
 
 
+def density_g(rho: np.ndarray) -> np.ndarray:
+    """rho(G) = (1/N) sum_j rho(r_j) exp(-i G.r_j): the density transform of Sec. III.A,
+    rho(G) = (1/Omega) int rho(r) e^{-iG.r} dr, on the grid (the integral becomes the
+    grid sum times Omega/N). Entry [i1][i2][i3] holds the G whose Miller indices satisfy
+    m = i mod N. The oracle's own forward 3-D transform, then the 1/N."""
+    r = np.ascontiguousarray(rho, dtype=np.float64)
+    return fft3d(r.astype(np.complex128), -1) / float(r.size)
+
+
+def grid_values_at(grid: np.ndarray, miller: np.ndarray) -> np.ndarray:
+    """Values of a [N1][N2][N3] grid array at Miller triples (index m mod N)."""
+    m = np.asarray(miller).reshape(-1, 3)
+    n = grid.shape
+    return grid[m[:, 0] % n[0], m[:, 1] % n[1], m[:, 2] % n[2]]
+
+
 # --------------------------------------------------------------------------
 # Nonlocal energy and force (Sec. III.A: the Kleinman-Bylander energy and its
 # derivative with respect to the atomic positions).
