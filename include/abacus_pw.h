@@ -237,6 +237,27 @@ int abacus_pw_density(const abacus_pw_problem *p, int precision, int nb, const v
                       double *rho, void *stream);
 
 /*
+ * Density transform of Sec. III.A on the grid: the reciprocal-space density
+ *   rho(G) = (1/N) sum_j rho(r_j) exp(-i G.r_j),   N = N1 N2 N3,
+ * the grid form of rho(G) = (1/Omega) int rho(r) e^{-iG.r} dr, for a real density
+ * on the grid (for example the output of abacus_pw_density). No plan is needed.
+ * fft       host int[3]: N1, N2, N3, each a length with a transform (abacus_pw_fft_supported).
+ * rho       device float64 [N1][N2][N3].
+ * ng        number of G vectors wanted.
+ * miller_g  device int32 [ng][3] Miller triples of the wanted G (for example the density sphere
+ *           |G|^2 < 4 ecutwfc). Any integers: a triple is read modulo the grid, so a G outside
+ *           the alias-free range 2|m_i| < N_i gets the value of its grid image. NULL: the whole
+ *           grid; then ng must equal N and rhog[(i1 N2 + i2) N3 + i3] holds the G with m = i mod N.
+ * rhog      device complex128 [ng], overwritten.
+ * Work space: with a G list, one complex128 grid (16 N bytes) per device, allocated by the
+ * library on first use and grown as needed (a call that grows it synchronises the device);
+ * calls with a G list that overlap on one device share it and must be ordered by the caller
+ * (one stream). Without a G list the transform runs in rhog itself.
+ * Asynchronous. Errors: ENULL_ARG, EBAD_SHAPE (ng < 0; ng != N without a list), EBAD_FFT_SIZE, EHIP.
+ */
+int abacus_pw_density_g(const int *fft, const double *rho, int ng, const int *miller_g, void *rhog, void *stream);
+
+/*
  * Nonlocal (Kleinman-Bylander) force on every atom, the derivative of the
  * projector energy with respect to the atomic positions (Sec. III.A). With the
  * projectors carrying the structure factor exp(-i (k+G).tau_a):

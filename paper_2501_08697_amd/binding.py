@@ -24,7 +24,7 @@ ERRORS = {
 }
 
 EXPORTS = ["abacus_pw_apply_h", "abacus_pw_davidson", "abacus_pw_cg", "abacus_pw_apply_h_backward", "abacus_pw_density",
-           "abacus_pw_chebyshev", "abacus_pw_chebyshev_coefficients", "abacus_pw_force_nl",
+           "abacus_pw_chebyshev", "abacus_pw_chebyshev_coefficients", "abacus_pw_force_nl", "abacus_pw_density_g",
            "abacus_pw_last_error",
            "abacus_pw_fft_supported", "abacus_pw_plan_reset", "abacus_pw_profile_enable",
            "abacus_pw_profile_read", "abacus_pw_set_tuning"]
@@ -63,6 +63,7 @@ def lib():
         L.abacus_pw_density.argtypes = [P, i, i, vp, vp, vp, vp]
         L.abacus_pw_chebyshev.argtypes = [P, i, i, vp, vp, vp, i, d, d, vp]
         L.abacus_pw_force_nl.argtypes = [P, i, i, vp, vp, vp, vp]
+        L.abacus_pw_density_g.argtypes = [vp, vp, i, vp, vp, vp]
         L.abacus_pw_chebyshev_coefficients.argtypes = [i, d, d, d, d, d, vp]
         L.abacus_pw_cg.argtypes = [P, i, vp, vp, d, i, vp, vp, vp]
         L.abacus_pw_last_error.argtypes = [C.c_char_p, i]
@@ -246,6 +247,31 @@ def density(dp: DeviceProblem, psi, occ, precision: int = FP64, nb: int | None =
     check(lib().abacus_pw_density(C.byref(cp), int(precision), int(nb), psi.data_ptr(), w.data_ptr(), rho.data_ptr(),
                                   _stream(stream)))
     return rho
+
+
+def density_g(rho, miller=None, stream=None, out=None):
+    """rho(G) = (1/N) sum_j rho(r_j) e^{-iG.r_j} (complex128): on the whole grid ([N1][N2][N3],
+    index m mod N) when miller is None, else at the Miller triples miller [ng][3] (int32)."""
+    import torch
+    if not isinstance(rho, torch.Tensor) or rho.dim() != 3:
+        raise AbacusPwError(-2, "rho must be a [N1][N2][N3] tensor")
+    _dev_tensor(rho, "rho", torch.float64, rho.numel())
+    fft = np.ascontiguousarray(rho.shape, dtype=np.int32)
+    if miller is None:
+        ng = rho.numel()
+        m = None
+        shape = tuple(rho.shape)
+    else:
+        m = torch.as_tensor(miller, dtype=torch.int32).to(rho.device).contiguous()
+        if m.dim() != 2 or m.shape[1] != 3:
+            raise AbacusPwError(-2, "miller must be [ng][3]")
+        ng = int(m.shape[0])
+        shape = (ng,)
+    y = (torch.empty(shape, dtype=torch.complex128, device=rho.device) if out is None
+         else _dev_tensor(out, "out", torch.complex128, ng, rho.device))
+    check(lib().abacus_pw_density_g(fft.ctypes.data, rho.data_ptr(), int(ng), None if m is None else m.data_ptr(),
+                                    y.data_ptr(), _stream(stream)))
+    return y
 
 
 def force_nl(dp: DeviceProblem, psi, occ, nb: int | None = None, stream=None):

@@ -217,3 +217,14 @@ def test_binding_checks_tensors_before_the_library(prob):
     with pytest.raises(B.AbacusPwError) as e:
         B.apply_h(dp, psi, precision=7)
     assert e.value.code == -7
+
+
+def test_density_g_rejects_before_device_access():
+    L = B.lib()
+    ok = np.array([16, 16, 16], dtype=np.int32)
+    bad = np.array([14, 16, 16], dtype=np.int32)
+    assert code_name(L.abacus_pw_density_g(bad.ctypes.data, FAKE, 14 * 256, None, FAKE, None)) == "EBAD_FFT_SIZE"
+    assert code_name(L.abacus_pw_density_g(ok.ctypes.data, FAKE, 100, None, FAKE, None)) == "EBAD_SHAPE"
+    assert code_name(L.abacus_pw_density_g(ok.ctypes.data, FAKE, -1, FAKE, FAKE, None)) == "EBAD_SHAPE"
+    assert code_name(L.abacus_pw_density_g(None, FAKE, 1, FAKE, FAKE, None)) == "ENULL_ARG"
+    assert code_name(L.abacus_pw_density_g(ok.ctypes.data, None, 1, FAKE, FAKE, None)) == "ENULL_ARG"
