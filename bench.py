@@ -1,21 +1,30 @@
 """Benchmark of the plane-wave H psi hot path on one MI355X.
 
-Workload (the FP64-vs-FP32 H psi case): simple-cubic cell a = 20.5 bohr,
-ecutwfc = 30 Ry (23,847 plane waves at Gamma), 72^3 grid, 64 atoms x 4
-Kleinman-Bylander projectors (s + p), 128 bands, seeded synthetic inputs.
+Headline workload (the batched uneven-k case, the largest that runs on one
+GPU): simple-cubic cell a = 30 bohr, ecutwfc = 40 Ry, 120^3 grid, the eight
+k-points of the {0, 1/2}^3 grid (spheres of 115,096 - 115,396 plane waves),
+216 atoms x 4 Kleinman-Bylander projectors (s + p), 512 bands per k-point,
+complex128, seeded synthetic inputs.
 
-One step = one H psi over all 128 bands in FP64: local term (three LDS
-transform passes on the grid) and nonlocal term (projection GEMM, D blocks,
-accumulation GEMM), inputs resident in HBM. `value` = band-applies per second
-= 128 * steps / time. The same JSON line carries the FP32 rate and its speedup,
-block Davidson time per k-point in FP64 (and mixed precision) to a 1e-8
-residual, the roofline of the dominant kernel (per-kernel times from HIP events
-recorded on the library's stream during the timed region), and the FP64 CPU
-oracle timed on this host.
+One step = one H psi over all 8 x 512 bands in FP64 (local term: three LDS
+transform passes on the grid, every k-point of a band batch in one launch per
+pass; nonlocal term: projection GEMM, D blocks, accumulation GEMM per
+k-point), issued as one abacus_pw_apply_h call captured in a HIP graph and
+replayed, inputs resident in HBM. `value` = band-applies per second =
+4096 * steps / time.
+
+The same JSON line carries: the roofline of the dominant kernel (per-kernel
+times from HIP events the library records on its stream in a profiled copy of
+the timed region), the local term against the pruned 5-pass byte model, the
+batched form against one call per k-point and the graph against eager calls,
+the launch gaps, complex64 / mixed precision rates, the 128^3 mixed-precision
+workload, the 72^3 FP64-vs-FP32 workload with its Davidson and CG legs, the
+band density, force, Chebyshev and adjoint legs, and the FP64 CPU oracle on a
+sample of the headline workload on this host.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-davidson] [--no-cg]
                       [--no-batched] [--no-autotune] [--no-density] [--no-backward] [--no-chebyshev]
-                      [--no-force] [--no-c4] [--c3]
+                      [--no-force] [--no-c4] [--no-c2] [--traffic-probe]
 """
 from __future__ import annotations
 
@@ -24,6 +33,7 @@ import hashlib
 import json
 import os
 import re
+import subprocess
 import sys
 import time
 
@@ -36,15 +46,19 @@ HBM_PEAK_GBS = 8000.0           # MI355X HBM3E, datasheet
 BF16_PEAK_TFLOPS = 2500.0       # MI355X dense BF16 MFMA
 FP64_PEAK_TFLOPS = 78.6         # MI355X dense FP64 (vector = matrix)
 FP32_PEAK_TFLOPS = 157.3
-WORKLOAD = "C2"
-WORKLOAD_DESC = ("cubic a=20.5 bohr, ecutwfc=30 Ry, 23847 PW, 72^3 grid, Gamma, 64 atoms x 4 KB projectors, "
-                 "128 bands, complex128")
+WORKLOAD = "C3"
+WORKLOAD_DESC = ("cubic a=30 bohr, ecutwfc=40 Ry, 120^3 grid, 8 k-points of the {0,1/2}^3 grid (uneven spheres), "
+                 "216 atoms x 4 KB projectors, 512 bands per k-point, complex128")
+
+
+def log(msg):
+    print(f"[bench {time.strftime('%H:%M:%S')}] {msg}", file=sys.stderr, flush=True)
 
 
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-davidson", action="store_true")
@@ -56,43 +70,54 @@ def parse():
     ap.add_argument("--no-chebyshev", action="store_true")
     ap.add_argument("--no-force", action="store_true")
     ap.add_argument("--no-c4", action="store_true")
-    ap.add_argument("--c3", action="store_true",
-                    help="also run the batched leg on the full C3 workload (8 k-points x 512 bands, 120^3; ~2 min)")
+    ap.add_argument("--no-c2", action="store_true", help="skip the 72^3 legs (H psi, density, force, Chebyshev, "
+                                                          "Davidson, CG)")
     ap.add_argument("--traffic-probe", action="store_true",
-                    help="run a plain 256 MiB copy and a few H psi steps only (for counter collection)")
+                    help="run a plain 256 MiB copy and a few H psi steps of the headline workload only "
+                         "(for counter collection)")
     return ap.parse_args()
 
 
-def kernel_model(name, prob, nb, launches):
-    """Algorithmic (bytes, flops) of ONE launch of a library kernel at this workload.
+def slab_points(prob):
+    """S = nslab N2 N3: the grid planes (union over k-points) that hold sphere points."""
+    n1, n2, n3 = prob.fft
+    m1 = prob.miller[:, 0]
+    return (int(m1.max()) - int(m1.min()) + 1) * n2 * n3
 
-    Per step (one H psi over nb bands), with cb = 16 bytes per complex128,
-    S = nslab * N2 * N3 (the slab: grid planes that hold sphere points) and npw
-    sphere points; a step's bytes are divided by the kernel's launches per step.
-      yz_inv : nb cb (npw + S)              read psi, write the slab planes
-      xpass  : nb cb 2 S + launches 8 N     slab in and out, V once per launch
-      yz_fwd : nb cb (S + 2 npw)            slab in, psi in (kinetic), H psi out
-      gemm_cn: flops 8 nproj nb npw         (bytes cb (nproj + nb) npw)
-      gemm_nn: flops 8 nb npw nproj         (bytes cb (nproj npw + 2 nb npw))
+
+def kernel_model(name, prob, nb, launches):
+    """Algorithmic (bytes, flops counted, flops executed) of ONE launch of a library kernel.
+
+    Per step (one H psi over nb bands at every k-point), with cb = 16 bytes per
+    complex128, S = nslab * N2 * N3 (the slab: grid planes that hold sphere
+    points), npw_k the sphere sizes; a step's figures are divided by the
+    kernel's launches per step.
+      yz_inv : nb cb sum_k (npw_k + S)          read psi, write the slab planes
+      xpass  : nb cb 2 S nk + launches 8 N      slab in and out, V once per launch
+      yz_fwd : nb cb sum_k (S + 2 npw_k)        slab in, psi in (kinetic), H psi out
+      gemm_cn: flops 8 nproj nb sum_k npw_k     counted complex flops; the kernel's 3M
+                                                products execute 6 nproj nb sum npw_k
+      gemm_nn: flops 8 nb sum_k npw_k nproj     likewise (6 executed)
     """
     cb = 16
     n1, n2, n3 = prob.fft
     N = n1 * n2 * n3
-    npw = int(prob.npw[0])
-    m1 = prob.miller[:, 0]
-    S = (int(m1.max()) - int(m1.min()) + 1) * n2 * n3
+    npw = [int(x) for x in prob.npw]
+    nk = len(npw)
+    S = slab_points(prob)
     npj = prob.nproj
+    tot = sum(npw)
     per_step = {
-        "yz_inv": (nb * cb * (npw + S), 0),
-        "xpass": (nb * cb * 2 * S + launches * 8 * N, 0),
-        "yz_fwd": (nb * cb * (S + 2 * npw), 0),
-        "gemm_cn": (cb * (npj + nb) * npw, 8 * npj * nb * npw),
-        "gemm_nn": (cb * (npj * npw + 2 * nb * npw), 8 * nb * npw * npj),
+        "yz_inv": (nb * cb * sum(n + S for n in npw), 0, 0),
+        "xpass": (nb * cb * 2 * S * nk + launches * 8 * N, 0, 0),
+        "yz_fwd": (nb * cb * sum(S + 2 * n for n in npw), 0, 0),
+        "gemm_cn": (cb * (npj + nb) * tot, 8 * npj * nb * tot, 6 * npj * nb * tot),
+        "gemm_nn": (cb * (npj * tot + 2 * nb * tot), 8 * nb * tot * npj, 6 * nb * tot * npj),
     }
     if name not in per_step:
-        return None, None
-    by, fl = per_step[name]
-    return by / launches, fl / launches
+        return None, None, None
+    by, fl, fe = per_step[name]
+    return by / launches, fl / launches, fe / launches
 
 
 def source_hash(paths):
@@ -113,31 +138,37 @@ KERNEL_SOURCES = {
 
 
 def local_model_bytes(prob):
-    """Per band: the pruned 5-pass model's bytes for the local term (z on the disk of
-    columns that hold sphere points, y on the slab, x on all; cb N 4 (f_disk + f_slab)
-    + 2 cb npw) and the bytes the three fused plane passes here move (4 cb S + 3 cb npw,
-    the disk staying in LDS)."""
+    """Per band, averaged over the k-points: the pruned 5-pass model's bytes for the
+    local term (z on the disk of columns that hold sphere points, y on the slab, x on
+    all; cb N 4 (f_disk + f_slab) + 2 cb npw) and the bytes the three fused plane
+    passes here move (4 cb S + 3 cb npw, the disk staying in LDS)."""
     cb = 16
     n1, n2, n3 = prob.fft
     N = n1 * n2 * n3
-    m = prob.miller_k(0) if hasattr(prob, "miller_k") else prob.miller
-    npw = int(prob.npw[0])
-    cols = len({(int(a) % n1, int(b) % n2) for a, b in zip(m[:, 0], m[:, 1])})
-    f_disk = cols / (n1 * n2)
-    nslab = int(m[:, 0].max()) - int(m[:, 0].min()) + 1
-    f_slab = nslab / n1
-    model = cb * N * 4 * (f_disk + f_slab) + 2 * cb * npw
-    ours = 4 * cb * nslab * n2 * n3 + 3 * cb * npw
-    return model, ours, f_disk, f_slab
+    off = prob.pw_offsets
+    model = ours = fd = fs = 0.0
+    nk = len(prob.npw)
+    for k in range(nk):
+        m = prob.miller[off[k]:off[k + 1]]
+        npw = int(prob.npw[k])
+        cols = len({(int(a) % n1, int(b) % n2) for a, b in zip(m[:, 0], m[:, 1])})
+        f_disk = cols / (n1 * n2)
+        nslab_k = int(m[:, 0].max()) - int(m[:, 0].min()) + 1
+        f_slab = nslab_k / n1
+        model += cb * N * 4 * (f_disk + f_slab) + 2 * cb * npw
+        ours += 4 * cb * slab_points(prob) + 3 * cb * npw
+        fd += f_disk
+        fs += f_slab
+    return model / nk, ours / nk, fd / nk, fs / nk
 
 
-def measured_traffic(kernel, bands_per_launch):
+def measured_traffic(kernel, bands_per_launch, workload=WORKLOAD):
     """HBM bytes per launch from the committed counter summary, if it matches the current source.
 
-    The summary was taken at its own launch shape (`bands_per_launch:` in the file);
-    the bytes scale with the bands one launch processes, so they are rescaled to
-    the launch shape timed here."""
-    path = os.path.join(ROOT, "profiles", f"traffic_{kernel}_{WORKLOAD}.txt")
+    The summary was taken at its own launch shape (`bands_per_launch:` in the file,
+    bands of all k-points one launch covers); the bytes scale with the bands one
+    launch processes, so they are rescaled to the launch shape timed here."""
+    path = os.path.join(ROOT, "profiles", f"traffic_{kernel}_{workload}.txt")
     if not os.path.exists(path):
         return None
     txt = open(path).read()
@@ -149,19 +180,59 @@ def measured_traffic(kernel, bands_per_launch):
     return float(b.group(1)) * bands_per_launch / int(nb.group(1))
 
 
-def cpu_baseline(prob, min_seconds=10.0, max_reps=8):
-    """The FP64 oracle's H psi over all bands, repeated until ~10 s of CPU work."""
+def host_cpu():
+    """CPU model, sockets, physical cores and logical CPUs of this host (lscpu)."""
+    info = {}
+    try:
+        txt = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=20).stdout
+        kv = dict(line.split(":", 1) for line in txt.splitlines() if ":" in line)
+        kv = {k.strip(): v.strip() for k, v in kv.items()}
+        info["model"] = kv.get("Model name")
+        sockets = int(kv.get("Socket(s)", "1"))
+        cps = int(kv.get("Core(s) per socket", "0"))
+        info["sockets"] = sockets
+        info["physical_cores"] = sockets * cps
+        info["logical_cpus"] = int(kv.get("CPU(s)", "0"))
+    except (OSError, ValueError, subprocess.SubprocessError):
+        pass
+    try:
+        info["affinity_cpus"] = len(os.sched_getaffinity(0))
+    except OSError:
+        pass
+    return info
+
+
+def cpu_baseline(prob, bands_per_k=2, one_thread_bands=1):
+    """The FP64 oracle's H psi on a sample of the headline workload: the first
+    bands_per_k bands of every k-point with all OpenMP threads, and one band of the
+    first k-point on one thread. Band-applies per second of each."""
     import oracle
-    nb = prob.nb
-    reps, dt = 0, 0.0
-    while reps < max_reps and (reps == 0 or dt < min_seconds):
+    nthreads = oracle.num_threads()
+    t_all, n_all = 0.0, 0
+    for k in range(prob.nk):
+        sub = oracle._single_k(prob, k)
+        rows = np.ascontiguousarray(prob.psi_k(k)[:bands_per_k]).reshape(-1)
         t0 = time.perf_counter()
-        oracle.apply_h(prob, prob.psi, nb=nb)
-        dt += time.perf_counter() - t0
-        reps += 1
-    return {"value": reps * nb / dt, "unit": "band-applies/s", "cores": oracle.num_threads(), "kind": "oracle",
-            "sample": f"{reps} FP64 H psi applications over all {nb} bands of the benchmark workload "
-                      f"({dt:.2f} s wall)"}
+        oracle.apply_h(sub, rows, nb=bands_per_k)
+        t_all += time.perf_counter() - t0
+        n_all += bands_per_k
+    log(f"cpu baseline: {n_all} bands on {nthreads} threads in {t_all:.1f} s")
+    oracle.set_num_threads(1)
+    try:
+        sub = oracle._single_k(prob, 0)
+        rows = np.ascontiguousarray(prob.psi_k(0)[:one_thread_bands]).reshape(-1)
+        t0 = time.perf_counter()
+        oracle.apply_h(sub, rows, nb=one_thread_bands)
+        t_one = time.perf_counter() - t0
+    finally:
+        oracle.set_num_threads(nthreads)
+    log(f"cpu baseline: {one_thread_bands} band on 1 thread in {t_one:.1f} s")
+    return {"value": n_all / t_all, "unit": "band-applies/s", "cores": nthreads, "kind": "oracle",
+            "sample": f"FP64 H psi of the first {bands_per_k} bands of each of the {prob.nk} k-points of the "
+                      f"benchmark workload ({n_all} band-applies, {t_all:.2f} s wall, {nthreads} OpenMP threads)",
+            "one_thread": {"value": one_thread_bands / t_one, "unit": "band-applies/s",
+                           "sample": f"{one_thread_bands} band of k-point 0 on 1 thread ({t_one:.2f} s wall)"},
+            "host": host_cpu()}
 
 
 def measured_hbm_peak(dev, nbytes=1 << 30, reps=5):
@@ -184,6 +255,74 @@ def measured_hbm_peak(dev, nbytes=1 << 30, reps=5):
     return 2 * nbytes / (best * 1e-3) / 1e9
 
 
+def kernel_rows(kern, prob, nb, steps, ms_step):
+    rows = {}
+    for name, (n, tot_ms) in kern.items():
+        avg = tot_ms / n
+        by, fl, fe = kernel_model(name, prob, nb, n / steps)
+        r = {"launches_per_step": n / steps, "avg_ms": avg, "share": tot_ms / (ms_step * steps),
+             "alg_bytes": by, "alg_flops": fl}
+        if fl:
+            r["tflops_counted"] = fl / (avg * 1e-3) / 1e12
+            r["tflops_executed"] = fe / (avg * 1e-3) / 1e12
+            r["frac_executed_fp64"] = r["tflops_executed"] / FP64_PEAK_TFLOPS
+        elif by:
+            r["gbs"] = by / (avg * 1e-3) / 1e9
+        rows[name] = r
+    return rows
+
+
+def roofline_of(rows, prob, nb, workload, mp):
+    """Roofline of the kernel with the largest share of the step. MFMA kernels are
+    priced at the flops they execute (the 3M complex products: 6 M N K), the
+    counted 8 M N K rate beside it as `achieved_counted`."""
+    dom = max(rows, key=lambda k: rows[k]["avg_ms"] * rows[k]["launches_per_step"])
+    d = rows[dom]
+    if d["alg_flops"]:
+        achieved = d["tflops_executed"]
+        roof = {"bound": "mfma", "achieved": achieved, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+                "frac": achieved / FP64_PEAK_TFLOPS, "achieved_counted": d["tflops_counted"]}
+    else:
+        achieved = d["alg_bytes"] / (d["avg_ms"] * 1e-3) / 1e9
+        roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": achieved / HBM_PEAK_GBS}
+    roof["kernel"] = dom
+    roof["avg_launch_ms"] = d["avg_ms"]
+    roof["alg_bytes_per_launch"] = d["alg_bytes"]
+    roof["traffic"] = measured_traffic(dom, prob.nk * nb / d["launches_per_step"], workload) \
+        if dom in KERNEL_SOURCES else None
+    if roof["bound"] == "hbm":
+        roof["measured_peak"] = mp             # 1 GiB device copy on this GPU
+        roof["frac_of_measured_peak"] = achieved / mp
+    return roof
+
+
+def local_term_of(rows, prob, nb, mp):
+    t_local = sum(rows[k]["avg_ms"] * rows[k]["launches_per_step"] for k in ("yz_inv", "xpass", "yz_fwd") if k in rows)
+    model_b, ours_b, f_disk, f_slab = local_model_bytes(prob)
+    nbt = nb * prob.nk
+    lt = {"ms_per_step": t_local, "f_disk": f_disk, "f_slab": f_slab,
+          "model_bytes_per_band": model_b, "fused_bytes_per_band": ours_b,
+          "effective_GBs": model_b * nbt / (t_local * 1e-3) / 1e9,
+          "physical_GBs": ours_b * nbt / (t_local * 1e-3) / 1e9, "peak": HBM_PEAK_GBS, "measured_peak": mp}
+    lt["frac_effective"] = lt["effective_GBs"] / HBM_PEAK_GBS
+    lt["frac_physical"] = lt["physical_GBs"] / HBM_PEAK_GBS
+    return lt
+
+
+def timed_calls(fn, steps, stream=None):
+    """ms per call of fn over `steps` calls, bracketed by synchronisations."""
+    import torch
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    a.record(stream) if stream is not None else a.record()
+    for _ in range(steps):
+        fn()
+    b.record(stream) if stream is not None else b.record()
+    torch.cuda.synchronize()
+    return a.elapsed_time(b) / steps
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -197,157 +336,176 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = torch.device("cuda:0")
+    log(f"generating {WORKLOAD}")
+    t0 = time.time()
     prob = W.make_problem(WORKLOAD)
-    nb = prob.nb
+    nb, nk = prob.nb, prob.nk
+    log(f"{WORKLOAD}: {time.time() - t0:.1f} s; npw {list(map(int, prob.npw))}")
     dp = B.DeviceProblem(prob, device=dev, static=True)   # operator data constant for the whole run
     x64 = torch.from_numpy(prob.psi).to(dev)
-    x32 = x64.to(torch.complex64)
     y64 = torch.empty_like(x64)
-    y32 = torch.empty_like(x32)
     stream = torch.cuda.current_stream()
 
-    def run(prec, x, y, steps):
-        for _ in range(steps):
-            B.apply_h(dp, x, prec, out=y)
+    def step():
+        B.apply_h(dp, x64, B.FP64, out=y64)
 
     if args.traffic_probe:
-        # calibration: one plain device copy of a known size, then the FP64 H psi with default tuning
+        # calibration: one plain device copy of a known size, then FP64 H psi steps with default tuning
         n = 256 << 20
         src = torch.ones(n // 8, dtype=torch.float64, device=dev)
         dst = torch.empty_like(src)
         dst.copy_(src)
         torch.cuda.synchronize()
-        run(B.FP64, x64, y64, max(1, args.steps))
+        for _ in range(max(1, args.steps)):
+            step()
         torch.cuda.synchronize()
         print(json.dumps({"traffic_probe": True, "copy_bytes": n, "steps": max(1, args.steps)}), flush=True)
         return
 
     # warm-up (builds the plan, allocates work space), then the launch-shape autotuner
-    run(B.FP64, x64, y64, args.warmup)
-    run(B.FP32, x32, y32, args.warmup)
+    for _ in range(args.warmup):
+        step()
     torch.cuda.synchronize()
+    log("warm-up done")
     tuning = None
     if not args.no_autotune:
         from paper_2501_08697_amd import autotune
-        cfg32, _ = autotune.tune(dp, x32, precision=B.FP32, use_cache=False)
-        cfg64, ms_tuned = autotune.tune(dp, x64, precision=B.FP64, use_cache=False)
-        tuning = {"fp64": cfg64, "fp32": cfg32}
-        run(B.FP64, x64, y64, args.warmup)
+        cfg64, ms_tuned = autotune.tune(dp, x64, precision=B.FP64, use_cache=False, reps=2, sweeps=1, trials=2)
+        tuning = {"fp64": cfg64, "ms_tuned": ms_tuned}
+        log(f"autotune: {cfg64} {ms_tuned:.2f} ms")
+        for _ in range(2):
+            step()
         torch.cuda.synchronize()
 
-    # timed FP64 region, per-kernel HIP events recorded on the library's stream
+    # the timed region: the H psi call replayed from a HIP graph
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        step()
+    g.replay()
+    torch.cuda.synchronize()
+    ms_graph = timed_calls(g.replay, args.steps, stream)
+    log(f"timed: {ms_graph:.2f} ms per step (graph replay)")
+
+    # profiled copy of the timed work: HIP events around every library launch, recorded on its stream
     B.profile_read()
     B.profile_enable(True)
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    e0.record(stream)
-    run(B.FP64, x64, y64, args.steps)
-    e1.record(stream)
-    torch.cuda.synchronize()
+    prof_steps = max(2, min(args.steps, 5))
+    ms_prof = timed_calls(step, prof_steps, stream)
     B.profile_enable(False)
     kern = B.profile_read()
-    ms64 = e0.elapsed_time(e1) / args.steps
-
-    # clean FP64 and FP32 regions (no per-kernel events)
-    def timed(prec, x, y):
-        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        torch.cuda.synchronize()
-        a.record(stream)
-        run(prec, x, y, args.steps)
-        b.record(stream)
-        torch.cuda.synchronize()
-        return a.elapsed_time(b) / args.steps
-
-    ms64_clean = timed(B.FP64, x64, y64)
-    if tuning:
-        B.set_tuning(**tuning["fp32"])
-    ms32 = timed(B.FP32, x32, y32)
-    if tuning:
-        B.set_tuning(**tuning["fp64"])
-
-    # dominant kernel and its roofline
-    rows = {}
-    for name, (n, tot_ms) in kern.items():
-        avg = tot_ms / n
-        by, fl = kernel_model(name, prob, nb, n / args.steps)
-        rows[name] = {"launches_per_step": n / args.steps, "avg_ms": avg, "share": tot_ms / (ms64 * args.steps),
-                      "alg_bytes": by, "alg_flops": fl}
-    dom = max(rows, key=lambda k: rows[k]["avg_ms"] * rows[k]["launches_per_step"])
-    d = rows[dom]
-    if d["alg_flops"]:
-        achieved = d["alg_flops"] / (d["avg_ms"] * 1e-3) / 1e12
-        roof = {"bound": "mfma", "achieved": achieved, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
-                "frac": achieved / FP64_PEAK_TFLOPS}
-    else:
-        achieved = d["alg_bytes"] / (d["avg_ms"] * 1e-3) / 1e9
-        roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": achieved / HBM_PEAK_GBS}
-    roof["kernel"] = dom
-    roof["traffic"] = measured_traffic(dom, nb / d["launches_per_step"])
+    ms_eager = timed_calls(step, max(3, args.steps // 4), stream)
+    rows = kernel_rows(kern, prob, nb, prof_steps, ms_prof)
+    sum_kernels = sum(r["avg_ms"] * r["launches_per_step"] for r in rows.values())
+    launches = sum(r["launches_per_step"] for r in rows.values())
     mp = measured_hbm_peak(dev)
-    if roof["bound"] == "hbm":
-        roof["measured_peak"] = mp             # 1 GiB device copy on this GPU
-        roof["frac_of_measured_peak"] = achieved / mp
-    # the local term as a whole (the three plane passes) against the pruned 5-pass model
-    t_local = sum(rows[k]["avg_ms"] * rows[k]["launches_per_step"] for k in ("yz_inv", "xpass", "yz_fwd") if k in rows)
-    model_b, ours_b, f_disk, f_slab = local_model_bytes(prob)
-    local_term = {"ms_per_step": t_local, "f_disk": f_disk, "f_slab": f_slab,
-                  "model_bytes_per_band": model_b, "fused_bytes_per_band": ours_b,
-                  "effective_GBs": model_b * nb / (t_local * 1e-3) / 1e9,
-                  "physical_GBs": ours_b * nb / (t_local * 1e-3) / 1e9, "peak": HBM_PEAK_GBS, "measured_peak": mp}
-    local_term["frac_effective"] = local_term["effective_GBs"] / HBM_PEAK_GBS
-    local_term["frac_physical"] = local_term["physical_GBs"] / HBM_PEAK_GBS
-    for r in rows.values():
-        if r["alg_flops"]:
-            r["tflops"] = r["alg_flops"] / (r["avg_ms"] * 1e-3) / 1e12
-        elif r["alg_bytes"]:
-            r["gbs"] = r["alg_bytes"] / (r["avg_ms"] * 1e-3) / 1e9
+    roof = roofline_of(rows, prob, nb, WORKLOAD, mp)
 
     out = {
         "metric": "Hψ band-applies/s, Davidson time/k-point vs plain FP64; % HBM & MFMA peak",
-        "value": nb / (ms64_clean * 1e-3),
+        "value": nk * nb / (ms_graph * 1e-3),
         "unit": "band-applies/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": ms64_clean,
-        "ms_per_step_with_kernel_events": ms64,
+        "ms_per_step": ms_graph,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": f"{WORKLOAD}: {WORKLOAD_DESC}", "bands": nb, "npw": int(prob.npw[0]),
-                   "fft": list(prob.fft), "nproj": prob.nproj, "kpoints": prob.nk},
+        "config": {"workload": f"{WORKLOAD}: {WORKLOAD_DESC}", "kpoints": nk, "bands_per_kpoint": nb,
+                   "npw": [int(x) for x in prob.npw], "fft": list(prob.fft), "nproj": prob.nproj,
+                   "issue": "one abacus_pw_apply_h call over all k-points, replayed from a HIP graph"},
         "roofline": roof,
-        "local_term": local_term,
-        "fp32": {"ms_per_step": ms32, "band_applies_per_s": nb / (ms32 * 1e-3), "speedup_vs_fp64": ms64_clean / ms32},
+        "local_term": local_term_of(rows, prob, nb, mp),
         "kernels": rows,
+        "launches": {"per_step": launches, "eager_ms_per_step": ms_eager,
+                     "profiled_ms_per_step": ms_prof, "sum_of_kernel_ms_per_step": sum_kernels,
+                     "gap_ms_per_step": ms_eager - sum_kernels,
+                     "gap_fraction": (ms_eager - sum_kernels) / ms_eager,
+                     "graph_vs_eager": ms_eager / ms_graph},
         "tuning": tuning,
     }
-
-    if not args.no_density:
-        out["density"] = density_times(B, W, dev, prob, dp, x64, args.steps)
-    if not args.no_c4:
-        out["mixed_precision_c4"] = c4_times(B, W, dev)
-    if not args.no_force:
-        out["force_nl"] = force_times(B, W, dev, prob, dp, x64, args.steps)
-    if not args.no_chebyshev:
-        out["chebyshev"] = chebyshev_times(B, W, dev, prob, dp, ms64_clean)
-    if not args.no_backward:
-        out["backward"] = backward_times(B, W, dev, max(5, args.steps // 4))
-    if not args.no_davidson:
-        out["davidson"] = davidson_times(B, W, dev)
-    if not args.no_cg:
-        out["cg_vs_davidson"] = cg_times(B, W, dev, out.get("davidson"))
     if not args.no_batched:
-        out["batched_kpoints"] = batched_times(B, W, dev, max(5, args.steps // 4))
-    if args.c3:
-        out["batched_kpoints_c3"] = batched_times(B, W, dev, 3, "C3")
-
+        log("batched vs per-k-point calls, precisions")
+        out["batched_kpoints"] = batched_times(B, W, dev, 3, prob=prob, dp=dp, x=x64)
+    del y64
+    torch.cuda.synchronize()
     if not args.no_cpu:
+        log("CPU baseline (oracle)")
         out["cpu_baseline"] = cpu_baseline(prob)
+    del x64, dp, prob
+    torch.cuda.empty_cache()
+    B.plan_reset()
+    B.set_tuning()
+
+    if not args.no_c4:
+        log("C4 mixed precision")
+        out["mixed_precision_c4"] = c4_times(B, W, dev)
+    if not args.no_c2:
+        log("C2 legs")
+        c2 = W.make_problem("C2")
+        dp2 = B.DeviceProblem(c2, device=dev, static=True)
+        x2 = torch.from_numpy(c2.psi).to(dev)
+        out["c2_h_psi"] = c2_times(B, dev, c2, dp2, x2, max(10, args.steps))
+        ms_c2 = out["c2_h_psi"]["fp64"]["ms_per_step"]
+        if not args.no_density:
+            out["density"] = density_times(B, W, dev, c2, dp2, x2, max(10, args.steps))
+        if not args.no_force:
+            out["force_nl"] = force_times(B, W, dev, c2, dp2, x2, max(10, args.steps))
+        if not args.no_chebyshev:
+            out["chebyshev"] = chebyshev_times(B, W, dev, c2, dp2, ms_c2)
+        del dp2, x2
+        B.plan_reset()
+        if not args.no_davidson:
+            log("C2 Davidson")
+            out["davidson"] = davidson_times(B, W, dev)
+        if not args.no_cg:
+            log("C2 CG")
+            out["cg_vs_davidson"] = cg_times(B, W, dev, out.get("davidson"))
+    if not args.no_backward:
+        log("C5 adjoint")
+        out["backward"] = backward_times(B, W, dev, max(5, args.steps // 4))
+    if not args.no_batched:
+        log("C5 batched")
+        out["batched_kpoints_c5"] = batched_times(B, W, dev, max(5, args.steps // 4), "C5")
     print(json.dumps(out), flush=True)
+
+
+def c2_times(B, dev, prob, dp, x64, steps):
+    """The FP64-vs-FP32 H psi workload (cubic a = 20.5 bohr, ecutwfc = 30 Ry, 72^3,
+    23,847 PW at Gamma, 64 atoms x 4 projectors, 128 bands): FP64 and FP32 per H psi
+    after the autotuner, with per-kernel rates."""
+    import torch
+    from paper_2501_08697_amd import autotune
+    nb = prob.nb
+    x32 = x64.to(torch.complex64)
+    y64, y32 = torch.empty_like(x64), torch.empty_like(x32)
+    for _ in range(3):
+        B.apply_h(dp, x64, B.FP64, out=y64)
+        B.apply_h(dp, x32, B.FP32, out=y32)
+    cfg32, _ = autotune.tune(dp, x32, precision=B.FP32, use_cache=False)
+    cfg64, _ = autotune.tune(dp, x64, precision=B.FP64, use_cache=False)
+    B.profile_read()
+    B.profile_enable(True)
+    ms_prof = timed_calls(lambda: B.apply_h(dp, x64, B.FP64, out=y64), steps)
+    B.profile_enable(False)
+    kern = B.profile_read()
+    ms64 = timed_calls(lambda: B.apply_h(dp, x64, B.FP64, out=y64), steps)
+    B.set_tuning(**cfg32)
+    ms32 = timed_calls(lambda: B.apply_h(dp, x32, B.FP32, out=y32), steps)
+    B.set_tuning()
+    rows = kernel_rows(kern, prob, nb, steps, ms_prof)
+    res = {"workload": "C2: cubic a=20.5 bohr, ecutwfc=30 Ry, 72^3, 23847 PW, Gamma, 64 atoms x 4 projectors, "
+                       "128 bands",
+           "fp64": {"ms_per_step": ms64, "band_applies_per_s": nb / (ms64 * 1e-3)},
+           "fp32": {"ms_per_step": ms32, "band_applies_per_s": nb / (ms32 * 1e-3), "speedup_vs_fp64": ms64 / ms32},
+           "kernels": rows, "tuning": {"fp64": cfg64, "fp32": cfg32}}
+    dom = max(rows, key=lambda k: rows[k]["avg_ms"] * rows[k]["launches_per_step"])
+    res["dominant"] = {"kernel": dom, **rows[dom]}
+    if dom in KERNEL_SOURCES:
+        res["dominant"]["traffic"] = measured_traffic(dom, nb / rows[dom]["launches_per_step"], "C2")
+    return res
 
 
 def density_times(B, W, dev, prob, dp, x, steps):
@@ -413,8 +571,10 @@ def c4_times(B, W, dev):
     256 atoms x 9 projectors (s+p+d, full D blocks), 1024 bands): one H psi in FP64, FP32,
     MIXED_FP32 (FP32 transforms and GEMMs, complex128 psi) and MIXED_BF16 (FP32 transforms,
     bf16 projector GEMMs with FP32 accumulation). GEMM rates count 8 nproj nb npw flops per
-    product against the peak of the product's own precision; errors are relative max-norm
-    against the FP64 result of the same GPU run."""
+    product (counted) and the flops the MFMA pipe executes (6 for the 3M FP64 / FP32 products,
+    8 for bf16), the fraction taken on the executed flops against the peak of the product's own
+    precision; errors are relative max-norm against the FP64 result of the same GPU run (the
+    bounds against the oracle at this size are in the GPU tests)."""
     import torch
     prob = W.make_problem("C4")
     B.set_tuning()
@@ -446,9 +606,14 @@ def c4_times(B, W, dev):
         for kn, (n, tot) in kern.items():
             if kn.startswith("gemm_") and "reduce" not in kn:
                 avg = tot / n
-                pk = BF16_PEAK_TFLOPS if kn.endswith("bf16") else (FP64_PEAK_TFLOPS if prec == B.FP64 else FP32_PEAK_TFLOPS)
+                bf = kn.endswith("bf16")
+                pk = BF16_PEAK_TFLOPS if bf else (FP64_PEAK_TFLOPS if prec == B.FP64 else FP32_PEAK_TFLOPS)
                 tf = flops / (avg * 1e-3) / 1e12
-                row[kn] = {"ms": avg, "tflops": tf, "peak": pk, "frac": tf / pk}
+                # executed: the FP64 / FP32 kernels form complex products with three real
+                # MFMA products (3M, 6 M N K flops); the bf16 kernel with four (8 M N K)
+                tx = tf * (1.0 if bf else 0.75)
+                row[kn] = {"ms": avg, "tflops_counted": tf, "tflops_executed": tx, "peak": pk, "frac": tx / pk,
+                           "frac_counted": tf / pk}
         yc = y.to(torch.complex128)
         if ref is None:
             ref = yc
@@ -602,22 +767,25 @@ def backward_times(B, W, dev, steps):
     return res
 
 
-def batched_times(B, W, dev, steps, workload="C5"):
-    """H psi over uneven k-points: C5 (Gamma, X, M, R; 96^3; 256 bands each; 512 projectors), or
-    C3 (the {0,1/2}^3 grid, eight spheres of 115,096 - 115,396 PW; 120^3; 512 bands each; 864 projectors).
+def batched_times(B, W, dev, steps, workload="C3", prob=None, dp=None, x=None):
+    """H psi over uneven k-points: C3 (the {0,1/2}^3 grid, eight spheres of 115,096 - 115,396 PW;
+    120^3; 512 bands each; 864 projectors) or C5 (Gamma, X, M, R; 96^3; 256 bands each; 512
+    projectors).
 
     Plain FP64 with one call per k-point, against every k-point in one call
     (one launch per pass per band batch), that call replayed from a HIP graph,
-    and the FP32 and MIXED_BF16 forms of the replayed call. Rates are
-    band-applies per second over all k-points.
+    and the complex64 (FP32), MIXED_FP32 and MIXED_BF16 forms of the replayed
+    call, each with its relative max-norm difference from the FP64 result of the
+    same GPU (context: the bounds against the oracle are in the GPU tests).
+    Rates are band-applies per second over all k-points.
     """
     import torch
-    prob = W.make_problem(workload)
+    if prob is None:
+        prob = W.make_problem(workload)
+        B.set_tuning()
+        dp = B.DeviceProblem(prob, device=dev, static=True)
+        x = torch.from_numpy(prob.psi).to(dev)
     nb, nk = prob.nb, prob.nk
-    B.set_tuning()
-    dp = B.DeviceProblem(prob, device=dev, static=True)
-    x = torch.from_numpy(prob.psi).to(dev)
-    x32 = x.to(torch.complex64)
     off = prob.pw_offsets
     subs = []
     for k in range(nk):
@@ -630,36 +798,40 @@ def batched_times(B, W, dev, steps, workload="C5"):
     def timed(fn):
         fn()
         torch.cuda.synchronize()
-        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        a.record()
-        for _ in range(steps):
-            fn()
-        b.record()
-        torch.cuda.synchronize()
-        return a.elapsed_time(b) / steps
+        return timed_calls(fn, steps)
 
     desc = {"C5": "C5: cubic a=24 bohr, ecutwfc=35 Ry, 96^3, k = G, X, M, R", "C3": "C3: cubic a=30 bohr, "
-            "ecutwfc=40 Ry, 120^3, k on the {0,1/2}^3 grid"}[workload]
+            "ecutwfc=40 Ry, 120^3, k on the {0,1/2}^3 grid"}[prob.name or workload]
     res = {"workload": desc + " (npw " + "/".join(str(int(n)) for n in prob.npw) + f"), {nb} bands each, "
                        f"{prob.natom} atoms x {prob.nproj // prob.natom} projectors"}
     t_perk = timed(lambda: [B.apply_h(dk, xk, out=yk) for dk, xk, yk in subs])
+    del subs
     y = torch.empty_like(x)
     t_batch = timed(lambda: B.apply_h(dp, x, out=y))
+    ref = y.clone()
     out = {}
-    for name, prec, xx in (("fp64", B.FP64, x), ("fp32", B.FP32, x32), ("mixed_bf16", B.MIXED_BF16, x)):
+    for name, prec in (("fp64", B.FP64), ("fp32", B.FP32), ("mixed_fp32", B.MIXED_FP32), ("mixed_bf16", B.MIXED_BF16)):
+        xx = x.to(torch.complex64) if prec == B.FP32 else x
         yy = torch.empty_like(xx)
         B.apply_h(dp, xx, prec, out=yy)
         torch.cuda.synchronize()
         g = torch.cuda.CUDAGraph()
         with torch.cuda.graph(g):
             B.apply_h(dp, xx, prec, out=yy)
-        out[name] = timed(g.replay)
+        ms = timed(g.replay)
+        err = float(((yy.to(torch.complex128) - ref).abs().max() / ref.abs().max()).item())
+        out[name] = (ms, err)
+        del g, yy, xx
     tot = nk * nb
     res["fp64_per_kpoint_calls"] = {"ms": t_perk, "band_applies_per_s": tot / (t_perk * 1e-3)}
-    res["fp64_batched"] = {"ms": t_batch, "band_applies_per_s": tot / (t_batch * 1e-3)}
-    for name, ms in out.items():
+    res["fp64_batched"] = {"ms": t_batch, "band_applies_per_s": tot / (t_batch * 1e-3),
+                           "speedup_vs_per_kpoint": t_perk / t_batch}
+    for name, (ms, err) in out.items():
         res[name + "_batched_graph"] = {"ms": ms, "band_applies_per_s": tot / (ms * 1e-3),
-                                        "speedup_vs_fp64_per_kpoint": t_perk / ms}
+                                        "speedup_vs_fp64_per_kpoint": t_perk / ms,
+                                        "speedup_vs_fp64_graph": out["fp64"][0] / ms,
+                                        "rel_diff_vs_fp64_gpu": err}
+    del y, ref
     return res
 
 
@@ -667,7 +839,7 @@ def cg_times(B, W, dev, dav):
     """Band-by-band preconditioned CG on the benchmark workload to the same 1e-8
     residual, FP64, beside the Davidson time of the same run."""
     import torch
-    prob = W.make_problem(WORKLOAD)
+    prob = W.make_problem("C2")
     dp = B.DeviceProblem(prob, device=dev)
     x = torch.from_numpy(prob.psi).to(dev)
     torch.cuda.synchronize()
@@ -686,7 +858,7 @@ def davidson_times(B, W, dev):
     modes (reduced-precision phase with FP32 or bf16 products, then FP64 refinement)."""
     import torch
     res = {}
-    prob = W.make_problem(WORKLOAD)
+    prob = W.make_problem("C2")
     dp = B.DeviceProblem(prob, device=dev)
     x = torch.from_numpy(prob.psi).to(dev)
     B.apply_h(dp, x)   # plan and work space built outside the timed solves

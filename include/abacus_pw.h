@@ -200,6 +200,36 @@ int abacus_pw_davidson(const abacus_pw_problem *p, int precision, int nb, void *
                        double tol, int max_iter, int ndim, int *iters, double *resid, void *stream);
 
 /*
+ * The dense FP64 steps of the Davidson iteration (Sec. III.B), callable on
+ * their own. Matrices are device complex128, row-major with a leading
+ * dimension; all work is enqueued on `stream`.
+ *
+ * abacus_pw_eigh_lowest: the lowest nw eigenpairs of the Hermitian n x n matrix
+ * A (both triangles stored; destroyed): Householder reduction to a real
+ * tridiagonal matrix, bisection on Sturm counts, inverse iteration, and the
+ * back-transformation. n <= 256 runs on one compute unit; larger orders reduce
+ * one column at a time with the matrix-vector product spread over the GPU and
+ * the rank-2k updates and the back-transformation on the matrix cores.
+ *   w     device float64 [nw], ascending.
+ *   vec   device complex128 [nw][ldv]: row j is the eigenvector of w[j] (unit norm; vectors of
+ *         eigenvalues closer than 1e-7 ||A|| are orthogonalised together, others are
+ *         orthogonal to about 1e-16 ||A|| / gap).
+ *   Limits 1 <= nw <= n <= 4096, ld >= n, ldv >= n. Asynchronous. Errors: ENULL_ARG, EBAD_SHAPE, EHIP.
+ *
+ * abacus_pw_cholesky: G = L L^H for a Hermitian positive definite n x n G; the lower triangle
+ * of G (diagonal included) is replaced by L, Linv (device [n][ldi]) receives L^{-1} (zero
+ * above the diagonal). n <= 136 factors in one work-group's LDS; larger orders in blocks of
+ * 64 columns (diagonal block in LDS, panel and trailing update on the matrix cores).
+ *   Limits 1 <= n <= 1024. Synchronises `stream`; returns ECHOLESKY when a pivot is not positive.
+ *
+ * Both hold a work space per device that the library allocates on first use and grows as
+ * needed (a call that grows it synchronises the device); calls that overlap on one device
+ * share it and must be ordered by the caller (one stream).
+ */
+int abacus_pw_eigh_lowest(int n, void *A, int ld, int nw, double *w, void *vec, int ldv, void *stream);
+int abacus_pw_cholesky(int n, void *G, int ld, void *Linv, int ldi, void *stream);
+
+/*
  * Adjoint of hpsi = H psi for a real loss L with upstream gradient
  * dY = dL/dRe(hpsi) + i dL/dIm(hpsi) (PyTorch's convention for complex tensors):
  *   grad_psi    = H dY                                   (H is Hermitian)

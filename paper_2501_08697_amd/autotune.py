@@ -64,7 +64,7 @@ def _time(dp, x, y, nb, precision, reps, trials=3):
 
 
 def tune(dp: B.DeviceProblem, x, nb: int | None = None, precision: int = B.FP64, reps: int = 10,
-         use_cache: bool = True, sweeps: int = 2, log=None):
+         use_cache: bool = True, sweeps: int = 2, log=None, trials: int = 3):
     """Returns (best config dict, best ms per H psi) and leaves the library set to it."""
     import torch
     nb = dp.prob.nb if nb is None else nb
@@ -84,14 +84,14 @@ def tune(dp: B.DeviceProblem, x, nb: int | None = None, precision: int = B.FP64,
     y = torch.empty_like(x)
     best = dict(DEFAULT)
     _apply(best)
-    best_ms = _time(dp, x, y, nb, precision, reps)
+    best_ms = _time(dp, x, y, nb, precision, reps, trials)
     for _ in range(sweeps):
         for name, values in CANDIDATES.items():
             for v in values:
                 cand = dict(best)
                 cand[name] = v
                 _apply(cand)
-                ms = _time(dp, x, y, nb, precision, reps)
+                ms = _time(dp, x, y, nb, precision, reps, trials)
                 if log:
                     log(f"autotune {cand} {ms:.4f} ms")
                 if ms < best_ms:

@@ -25,6 +25,7 @@ ERRORS = {
 
 EXPORTS = ["abacus_pw_apply_h", "abacus_pw_davidson", "abacus_pw_cg", "abacus_pw_apply_h_backward", "abacus_pw_density",
            "abacus_pw_chebyshev", "abacus_pw_chebyshev_coefficients", "abacus_pw_force_nl", "abacus_pw_density_g",
+           "abacus_pw_eigh_lowest", "abacus_pw_cholesky",
            "abacus_pw_last_error",
            "abacus_pw_fft_supported", "abacus_pw_plan_reset", "abacus_pw_profile_enable",
            "abacus_pw_profile_read", "abacus_pw_set_tuning"]
@@ -64,6 +65,8 @@ def lib():
         L.abacus_pw_chebyshev.argtypes = [P, i, i, vp, vp, vp, i, d, d, vp]
         L.abacus_pw_force_nl.argtypes = [P, i, i, vp, vp, vp, vp]
         L.abacus_pw_density_g.argtypes = [vp, vp, i, vp, vp, vp]
+        L.abacus_pw_eigh_lowest.argtypes = [i, vp, i, i, vp, vp, i, vp]
+        L.abacus_pw_cholesky.argtypes = [i, vp, i, vp, i, vp]
         L.abacus_pw_chebyshev_coefficients.argtypes = [i, d, d, d, d, d, vp]
         L.abacus_pw_cg.argtypes = [P, i, vp, vp, d, i, vp, vp, vp]
         L.abacus_pw_last_error.argtypes = [C.c_char_p, i]
@@ -272,6 +275,33 @@ def density_g(rho, miller=None, stream=None, out=None):
     check(lib().abacus_pw_density_g(fft.ctypes.data, rho.data_ptr(), int(ng), None if m is None else m.data_ptr(),
                                     y.data_ptr(), _stream(stream)))
     return y
+
+
+def eigh_lowest(a, nw: int, stream=None):
+    """Lowest nw eigenpairs of the Hermitian complex128 [n][n] device matrix a (destroyed):
+    (w [nw] float64 ascending, vec [nw][n] complex128, rows = eigenvectors)."""
+    import torch
+    if not isinstance(a, torch.Tensor) or a.dim() != 2 or a.shape[0] != a.shape[1]:
+        raise AbacusPwError(-2, "a must be a square [n][n] tensor")
+    n = int(a.shape[0])
+    _dev_tensor(a, "a", torch.complex128, n * n)
+    w = torch.empty(nw, dtype=torch.float64, device=a.device)
+    v = torch.empty((nw, n), dtype=torch.complex128, device=a.device)
+    check(lib().abacus_pw_eigh_lowest(n, a.data_ptr(), n, int(nw), w.data_ptr(), v.data_ptr(), n, _stream(stream)))
+    return w, v
+
+
+def cholesky(g, stream=None):
+    """G = L L^H for a Hermitian positive definite complex128 [n][n] device matrix: the lower
+    triangle of g becomes L (in place); returns Linv = L^{-1}."""
+    import torch
+    if not isinstance(g, torch.Tensor) or g.dim() != 2 or g.shape[0] != g.shape[1]:
+        raise AbacusPwError(-2, "g must be a square [n][n] tensor")
+    n = int(g.shape[0])
+    _dev_tensor(g, "g", torch.complex128, n * n)
+    li = torch.zeros((n, n), dtype=torch.complex128, device=g.device)
+    check(lib().abacus_pw_cholesky(n, g.data_ptr(), n, li.data_ptr(), n, _stream(stream)))
+    return li
 
 
 def force_nl(dp: DeviceProblem, psi, occ, nb: int | None = None, stream=None):

@@ -9,6 +9,7 @@
 
 #include "abacus_pw.h"
 #include "common.hpp"
+#include "dense.hpp"
 #include "hamiltonian.hpp"
 #include "local.hpp"
 #include "plan.hpp"
@@ -86,6 +87,29 @@ static int prof_collect() {
 }
 
 int plan_reset_all();
+
+// Work space of the dense entry points, one per device, grown as needed.
+namespace {
+constexpr int kMaxDevicesDense = 64;
+std::mutex g_dense_mu;
+DeviceBuffer g_dense_ws[kMaxDevicesDense];
+DeviceBuffer g_dense_info[kMaxDevicesDense];
+
+int dense_workspace(size_t bytes, void **ws, int **info) {
+    int dev = 0;
+    APW_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevicesDense) return set_error(ABACUS_PW_EINTERNAL, "device index out of range");
+    std::lock_guard<std::mutex> l(g_dense_mu);
+    if (g_dense_ws[dev].bytes < bytes) {
+        APW_HIP(hipDeviceSynchronize());   // earlier calls may still use the old buffer
+        APW_TRY(g_dense_ws[dev].ensure(bytes));
+    }
+    APW_TRY(g_dense_info[dev].ensure(sizeof(int)));
+    *ws = g_dense_ws[dev].ptr;
+    *info = g_dense_info[dev].as<int>();
+    return ABACUS_PW_OK;
+}
+}  // namespace
 
 }  // namespace apw
 
@@ -233,6 +257,38 @@ int abacus_pw_chebyshev_coefficients(int order, double emin, double emax, double
             !(kt > 0.0) || !std::isfinite(kt) || !(power > 0.0) || !std::isfinite(power))
             return set_error(ABACUS_PW_EBAD_SHAPE, "need finite emin < emax, mu, kt > 0 and power > 0");
         fermi_coefficients(order, emin, emax, mu, kt, power, coef);
+        return ABACUS_PW_OK;
+    });
+}
+
+int abacus_pw_eigh_lowest(int n, void *A, int ld, int nw, double *w, void *vec, int ldv, void *stream) {
+    return guarded([&]() -> int {
+        if (!A || !w || !vec) return set_error(ABACUS_PW_ENULL_ARG, "A, w and vec are required");
+        if (n < 1 || n > kMaxSub || nw < 1 || nw > n || ld < n || ldv < n)
+            return set_error(ABACUS_PW_EBAD_SHAPE, "need 1 <= nw <= n <= 4096, ld >= n, ldv >= n");
+        void *ws = nullptr;
+        int *info = nullptr;
+        APW_TRY(dense_workspace(heev_scratch_bytes(n), &ws, &info));
+        return heev_lowest(n, static_cast<z64 *>(A), ld, nw, w, static_cast<z64 *>(vec), ldv, ws,
+                           static_cast<hipStream_t>(stream));
+    });
+}
+
+int abacus_pw_cholesky(int n, void *G, int ld, void *Linv, int ldi, void *stream) {
+    return guarded([&]() -> int {
+        if (!G || !Linv) return set_error(ABACUS_PW_ENULL_ARG, "G and Linv are required");
+        if (n < 1 || n > kMaxChol || ld < n || ldi < n)
+            return set_error(ABACUS_PW_EBAD_SHAPE, "need 1 <= n <= 1024, ld >= n, ldi >= n");
+        void *ws = nullptr;
+        int *info = nullptr;
+        hipStream_t st = static_cast<hipStream_t>(stream);
+        APW_TRY(dense_workspace(potrf_scratch_bytes(n), &ws, &info));
+        APW_TRY(potrf_inv(n, static_cast<z64 *>(G), ld, static_cast<z64 *>(Linv), ldi, info, ws, st));
+        int h = 0;
+        APW_HIP(hipMemcpyAsync(&h, info, sizeof(int), hipMemcpyDeviceToHost, st));
+        APW_HIP(hipStreamSynchronize(st));
+        if (h != 0)
+            return set_error(ABACUS_PW_ECHOLESKY, "matrix is not positive definite (pivot " + std::to_string(h) + ")");
         return ABACUS_PW_OK;
     });
 }

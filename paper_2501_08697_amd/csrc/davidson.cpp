@@ -37,7 +37,8 @@ namespace apw {
 namespace {
 
 struct Buffers {
-    DeviceBuffer V, HV, Xc, Wc, R, Y, Hs, Hw, coef, C, G, Linv, part, theta, rn2, ek, n0, n1, act, idx, info, heev, bfs;
+    DeviceBuffer V, HV, Xc, Wc, R, Y, Hs, Hw, coef, C, G, Linv, part, theta, rn2, ek, n0, n1, act, idx, info, heev, bfs,
+        chol;
 };
 
 int d2h(void *dst, const void *src, size_t bytes, hipStream_t st) {
@@ -64,7 +65,7 @@ int cholqr_rows(int m, int npw, z64 *T, z64 *Y, Buffers &b, int passes, hipStrea
     z64 *G = b.G.as<z64>(), *Linv = b.Linv.as<z64>();
     for (int pass = 0; pass < passes; ++pass) {
         APW_TRY(gemm_cn(0, m, m, npw, T, npw, T, npw, G, m, 1.0, 0.0, b.part.ptr, 0, st));
-        APW_TRY(potrf_inv(m, G, m, Linv, m, b.info.as<int>(), st));
+        APW_TRY(potrf_inv(m, G, m, Linv, m, b.info.as<int>(), b.chol.ptr, st));
         int info = 0;
         APW_TRY(d2h(&info, b.info.ptr, sizeof(int), st));
         if (info != 0) {
@@ -76,7 +77,7 @@ int cholqr_rows(int m, int npw, z64 *T, z64 *Y, Buffers &b, int passes, hipStrea
             const double shift = 11.0 * ((double)m * npw + (double)m * (m + 1)) * 2.220446049250313e-16 * tr;
             APW_TRY(gemm_cn(0, m, m, npw, T, npw, T, npw, G, m, 1.0, 0.0, b.part.ptr, 0, st));
             APW_TRY(dav_add_diag(m, G, m, shift, st));
-            APW_TRY(potrf_inv(m, G, m, Linv, m, b.info.as<int>(), st));
+            APW_TRY(potrf_inv(m, G, m, Linv, m, b.info.as<int>(), b.chol.ptr, st));
             APW_TRY(d2h(&info, b.info.ptr, sizeof(int), st));
             if (info != 0) return set_error(ABACUS_PW_ECHOLESKY, "Gram matrix is not positive definite");
             ++passes;   // a shifted pass is followed by one more plain pass
@@ -121,7 +122,8 @@ int davidson_k(const abacus_pw_problem &p, Plan &P, int k, int hprec, int nb, z6
                Result &res, hipStream_t st) {
     const int npw = P.k[k].npw, nmax = ndim * nb;
     const double *kin = P.k[k].kin;
-    if (nmax > kMaxSub) return set_error(ABACUS_PW_EBAD_SHAPE, "ndim * nb exceeds the device eigensolver limit (1024)");
+    if (nmax > kMaxSub) return set_error(ABACUS_PW_EBAD_SHAPE, "ndim * nb exceeds the device eigensolver limit (4096)");
+    if (nb > kMaxChol) return set_error(ABACUS_PW_EBAD_SHAPE, "nb exceeds the device Cholesky limit (1024)");
     const size_t vb = sizeof(z64) * (size_t)npw;
     const int vrows = nmax + nb;   // locked rows (at most nb - 1), then the basis
     APW_TRY(b.V.ensure(vb * vrows));
@@ -146,6 +148,7 @@ int davidson_k(const abacus_pw_problem &p, Plan &P, int k, int hprec, int nb, z6
     APW_TRY(b.idx.ensure(sizeof(int) * nb));
     APW_TRY(b.info.ensure(sizeof(int)));
     APW_TRY(b.heev.ensure(heev_scratch_bytes(nmax)));
+    APW_TRY(b.chol.ensure(potrf_scratch_bytes(nb)));
     z64 *V = b.V.as<z64>(), *HV = b.HV.as<z64>(), *Xc = b.Xc.as<z64>(), *Wc = b.Wc.as<z64>(), *R = b.R.as<z64>();
     z64 *Y = b.Y.as<z64>(), *Hs = b.Hs.as<z64>(), *Hw = b.Hw.as<z64>(), *C = b.C.as<z64>();
     double *theta = b.theta.as<double>();

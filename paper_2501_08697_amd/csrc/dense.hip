@@ -59,7 +59,7 @@ __device__ __forceinline__ double wave_sum(double v) {
 }
 
 // G (n x n, ld) Hermitian positive definite; its lower triangle is replaced
-// by L with G = L L^H (right-looking, in global memory; any n <= kMaxSub).
+// by L with G = L L^H (right-looking, in global memory, one work-group).
 // info = 0, or k + 1 when the k-th pivot is not positive.
 __global__ __launch_bounds__(kNT) void k_potrf(int n, z64 *G, int ld, int *info) {
     const int tid = threadIdx.x;
@@ -209,8 +209,8 @@ constexpr int kSymvBatch = 8;    // loads in flight per thread in the symmetric 
 template <bool kLdsPanel>
 __global__ __launch_bounds__(kNT) void k_hetrd(int n, z64 *A, int ld, double *d, double *e, z64 *tau, z64 *VW,
                                                z64 *Vr) {
-    __shared__ z64 xs[kMaxSub];        // column k from the diagonal down, panel updates applied
-    __shared__ z64 a0s[kMaxSub];       // first column of A22 (conjugated row)
+    __shared__ z64 xs[kSmallSub];      // column k from the diagonal down, panel updates applied
+    __shared__ z64 a0s[kSmallSub];     // first column of A22 (conjugated row)
     __shared__ z64 part[kNT];          // partial sums of A22 x
     __shared__ z64 dots[2 * kPanel];   // W^H x, V^H x over rows k+2 ..
     __shared__ z64 ybc;                // y_0, for the next column's update
@@ -691,23 +691,35 @@ __global__ __launch_bounds__(256) void k_unmtr(int n, const z64 *__restrict__ Vr
 }
 
 // ---------------------------------------------------------------- drivers --
-int potrf_inv(int n, z64 *G, int ld, z64 *Linv, int ldi, int *info_dev, hipStream_t st) {
-    if (n > kMaxSub) return set_error(ABACUS_PW_EBAD_SHAPE, "Cholesky size above the device limit");
-    KernelTimer kt("potrf_inv", st);
-    if (n <= kCholLds) {
-        const size_t lds = sizeof(z64) * (size_t)tri(n);
-        static bool attr = false;
-        if (!attr) {
-            APW_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(k_potrf_lds),
-                                        hipFuncAttributeMaxDynamicSharedMemorySize,
-                                        (int)(sizeof(z64) * (size_t)tri(kCholLds))));
-            attr = true;
-        }
-        hipLaunchKernelGGL(k_potrf_lds, dim3(1), dim3(kNT), lds, st, n, G, ld, info_dev);
+size_t potrf_large_scratch_bytes(int n);                                       // dense_large.hip
+int potrf_large(int n, z64 *G, int ld, int *info_dev, void *scratch, hipStream_t st);
+size_t heev_large_scratch_bytes(int n, int nw);
+int heev_lowest_large(int n, z64 *A, int ld, int nw, double *w, z64 *coef, int ldc, void *scratch, hipStream_t st);
+
+size_t potrf_scratch_bytes(int n) { return n >= kLargeCholMin ? potrf_large_scratch_bytes(n) : 256; }
+
+int potrf_inv(int n, z64 *G, int ld, z64 *Linv, int ldi, int *info_dev, void *scratch, hipStream_t st) {
+    if (n > kMaxChol) return set_error(ABACUS_PW_EBAD_SHAPE, "Cholesky size above the device limit (1024)");
+    if (n >= kLargeCholMin) {
+        APW_TRY(potrf_large(n, G, ld, info_dev, scratch, st));
     } else {
-        hipLaunchKernelGGL(k_potrf, dim3(1), dim3(kNT), 0, st, n, G, ld, info_dev);
+        KernelTimer kt("potrf_inv", st);
+        if (n <= kCholLds) {
+            const size_t lds = sizeof(z64) * (size_t)tri(n);
+            static bool attr = false;
+            if (!attr) {
+                APW_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(k_potrf_lds),
+                                            hipFuncAttributeMaxDynamicSharedMemorySize,
+                                            (int)(sizeof(z64) * (size_t)tri(kCholLds))));
+                attr = true;
+            }
+            hipLaunchKernelGGL(k_potrf_lds, dim3(1), dim3(kNT), lds, st, n, G, ld, info_dev);
+        } else {
+            hipLaunchKernelGGL(k_potrf, dim3(1), dim3(kNT), 0, st, n, G, ld, info_dev);
+        }
+        APW_TRY(check_launch("potrf"));
     }
-    APW_TRY(check_launch("potrf"));
+    KernelTimer kt("trinv", st);
     const dim3 grid(ceil_div(n, 4)), block(256);
     const int R = ceil_div(n, 64);
     if (R <= 1) hipLaunchKernelGGL(k_trinv<1>, grid, block, 0, st, n, G, ld, Linv, ldi, info_dev);
@@ -720,17 +732,35 @@ int potrf_inv(int n, z64 *G, int ld, z64 *Linv, int ldi, int *info_dev, hipStrea
 
 static int stein_slots(int nw) { return ceil_div(nw, 64) * 64; }
 
-// d, e (n doubles each), tau (n), the panel vectors V, W of the tridiagonal
-// reduction (2 kPanel n), the reflector rows Vr (n x n), Z (n x n doubles) and
-// the inverse-iteration arrays (6 n S doubles)
+size_t stein_work_bytes(int n, int nw) { return (size_t)6 * n * stein_slots(nw) * sizeof(double) + 256; }
+
+int stebz_values(int n, const double *d, const double *e, int nw, double *w, hipStream_t st) {
+    KernelTimer kt("stebz", st);
+    hipLaunchKernelGGL(k_stebz, dim3(ceil_div(nw, 4)), dim3(256), 0, st, n, d, e, nw, w);
+    return check_launch("stebz");
+}
+
+int stein_vectors(int n, const double *d, const double *e, int nw, const double *w, double *Z, int ldz, void *work,
+                  size_t work_bytes, hipStream_t st) {
+    if (work_bytes < stein_work_bytes(n, nw)) return set_error(ABACUS_PW_EINTERNAL, "inverse-iteration work space");
+    KernelTimer kt("stein", st);
+    hipLaunchKernelGGL(k_stein, dim3(ceil_div(nw, 64)), dim3(64), 0, st, n, d, e, nw, w, Z, ldz,
+                       static_cast<double *>(work));
+    return check_launch("stein");
+}
+
+// Small orders: d, e (n doubles each), tau (n), the panel vectors V, W of the tridiagonal
+// reduction (2 kPanel n), the reflector rows Vr (n x n), Z (n x n doubles) and the
+// inverse-iteration arrays (6 n S doubles). Large orders: the layout of dense_large.hip.
 size_t heev_scratch_bytes(int n) {
+    if (n >= kLargeHeevMin) return heev_large_scratch_bytes(n, n) + stein_work_bytes(n, n) + 256;
     return (size_t)n * (2 * sizeof(double) + sizeof(z64)) + (size_t)2 * kPanel * n * sizeof(z64) +
-           (size_t)n * n * sizeof(z64) + (size_t)n * n * sizeof(double) +
-           (size_t)6 * n * stein_slots(n) * sizeof(double) + 1024;
+           (size_t)n * n * sizeof(z64) + (size_t)n * n * sizeof(double) + stein_work_bytes(n, n) + 1024;
 }
 
 int heev_lowest(int n, z64 *A, int ld, int nw, double *w, z64 *coef, int ldc, void *scratch, hipStream_t st) {
-    if (n > kMaxSub) return set_error(ABACUS_PW_EBAD_SHAPE, "subspace size above the device eigensolver limit");
+    if (n > kMaxSub) return set_error(ABACUS_PW_EBAD_SHAPE, "subspace size above the device eigensolver limit (4096)");
+    if (n >= kLargeHeevMin) return heev_lowest_large(n, A, ld, nw, w, coef, ldc, scratch, st);
     char *s = static_cast<char *>(scratch);
     double *d = reinterpret_cast<double *>(s);
     double *e = d + n;
@@ -745,16 +775,8 @@ int heev_lowest(int n, z64 *A, int ld, int nw, double *w, z64 *coef, int ldc, vo
         else hipLaunchKernelGGL(k_hetrd<false>, dim3(1), dim3(kNT), 0, st, n, A, ld, d, e, tau, VW, Vr);
         APW_TRY(check_launch("hetrd"));
     }
-    {
-        KernelTimer kt("stebz", st);
-        hipLaunchKernelGGL(k_stebz, dim3(ceil_div(nw, 4)), dim3(256), 0, st, n, d, e, nw, w);
-        APW_TRY(check_launch("stebz"));
-    }
-    {
-        KernelTimer kt("stein", st);
-        hipLaunchKernelGGL(k_stein, dim3(ceil_div(nw, 64)), dim3(64), 0, st, n, d, e, nw, w, Z, n, work);
-        APW_TRY(check_launch("stein"));
-    }
+    APW_TRY(stebz_values(n, d, e, nw, w, st));
+    APW_TRY(stein_vectors(n, d, e, nw, w, Z, n, work, stein_work_bytes(n, nw), st));
     {
         KernelTimer kt("unmtr", st);
         const dim3 grid(ceil_div(nw, 4)), block(256);

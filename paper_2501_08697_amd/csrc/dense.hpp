@@ -5,11 +5,17 @@
 
 namespace apw {
 
-constexpr int kMaxSub = 1024;   // largest Cholesky / eigen-problem order handled on the device
+constexpr int kSmallSub = 1024;  // largest order of the one-CU kernels (their LDS arrays)
+constexpr int kMaxSub = 4096;    // largest eigen-problem order handled on the device
+constexpr int kMaxChol = 1024;   // largest Cholesky order (the explicit inverse holds a column in registers)
+constexpr int kLargeHeevMin = 257;   // orders from here on take the multi-CU eigensolver (dense_large.hip)
+constexpr int kLargeCholMin = 137;   // orders from here on take the blocked multi-CU Cholesky
 
 // G (n x n, row-major, ld) Hermitian positive definite: lower triangle := L with
 // G = L L^H; Linv (ldi) := L^{-1}. *info_dev = 0 or k + 1 for a failed pivot.
-int potrf_inv(int n, z64 *G, int ld, z64 *Linv, int ldi, int *info_dev, hipStream_t st);
+// scratch: potrf_scratch_bytes(n) bytes of device memory (unused for small n).
+int potrf_inv(int n, z64 *G, int ld, z64 *Linv, int ldi, int *info_dev, void *scratch, hipStream_t st);
+size_t potrf_scratch_bytes(int n);
 
 size_t heev_scratch_bytes(int n);
 

@@ -169,3 +169,51 @@ def test_rejects_bad_sizes():
     with pytest.raises(b.AbacusPwError) as e:
         b.davidson(dp, x, ndim=1)
     assert e.value.name == "EBAD_SHAPE"
+
+
+def test_subspace_2048_against_dense():
+    """1024 bands at ndim 2: the 2048 x 2048 Rayleigh-Ritz problem and 1024 x 1024 Cholesky
+    factors of the largest workload, on a cell small enough for a dense eigensolve of its
+    4,139-plane-wave H (a = 14 bohr, ecutwfc = 20 Ry, 24^3, Gamma)."""
+    p = W.make_problem(W.tiny_config(a=14.0, ecut=20.0, fft=24, nb=1024, natom=4, seed=21))
+    print(f"[davidson] npw {p.npw[0]}", flush=True)
+    eig, psi, res, its, st = gpu_davidson(p, 1e-9, 300)
+    assert st == 0 and np.max(res) < 1e-9
+    ev = np.linalg.eigvalsh(oracle.dense_h(p, 0))[:1024]
+    np.testing.assert_allclose(eig[0], ev, atol=1e-11)
+    check_vectors(p, psi, eig, 1024, 1.5e-9)
+
+
+@pytest.mark.parametrize("nb,ndim", [(160, 2), (300, 3)])
+def test_multi_cu_subspace_c1_against_dense(nb, ndim):
+    """Subspaces of 320 and 900 (the multi-CU eigensolver; Cholesky of 160 and 300 rows in
+    blocks) on the 32^3 workload, against its dense spectrum."""
+    p = W.make_problem("C1", nb=nb)
+    eig, psi, res, its, st = gpu_davidson(p, 1e-10, 400, ndim=ndim)
+    assert st == 0 and np.max(res) < 1e-10
+    ev = np.linalg.eigvalsh(oracle.dense_h(p, 0))[:nb]
+    np.testing.assert_allclose(eig[0], ev, atol=1e-11)
+    check_vectors(p, psi, eig, nb, 1.5e-10)
+
+
+def test_c5_to_1e8_oracle_residuals():
+    """The differentiation workload (96^3, four uneven k-points, 256 bands each, subspace 512)
+    to a 1e-8 residual; the oracle recomputes H psi on a sample of the GPU's vectors (every
+    16th band and the last of each k-point), all vectors are checked for orthonormality."""
+    p = W.make_problem("C5")
+    eig, psi, res, its, st = gpu_davidson(p, 1e-8, 300)
+    assert st == 0 and np.max(res) < 1e-8
+    off = p.pw_offsets
+    nb = p.nb
+    sample = sorted(set(range(0, nb, 16)) | {nb - 1})
+    for k in range(p.nk):
+        assert np.all(np.diff(eig[k]) >= -1e-12)
+        x = psi[nb * off[k]: nb * off[k + 1]].reshape(nb, -1)
+        assert np.max(np.abs(x.conj() @ x.T - np.eye(nb))) < 1e-12
+        xs = np.ascontiguousarray(x[sample])
+        hx = oracle.apply_h(oracle._single_k(p, k), xs.reshape(-1), nb=len(sample)).reshape(len(sample), -1)
+        rq = np.real(np.sum(xs.conj() * hx, axis=1))
+        assert np.max(np.abs(rq - eig[k][sample])) < 1e-10 * max(1.0, np.max(np.abs(eig[k])))
+        r = np.linalg.norm(hx - eig[k][sample][:, None] * xs, axis=1)
+        assert np.max(r) < 1.5e-8, (k, np.max(r))
+        print(f"[davidson] C5 k={k}: oracle residual max {np.max(r):.2e}, iterations {its[k]}", flush=True)
