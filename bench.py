@@ -72,6 +72,9 @@ def parse():
     ap.add_argument("--no-c4", action="store_true")
     ap.add_argument("--no-c2", action="store_true", help="skip the 72^3 legs (H psi, density, force, Chebyshev, "
                                                           "Davidson, CG)")
+    ap.add_argument("--c4-davidson", action="store_true",
+                    help="also run Davidson to a 1e-8 residual on the 128^3, 1024-band workload in FP64 and "
+                         "MIXED_BF16 (several minutes)")
     ap.add_argument("--traffic-probe", action="store_true",
                     help="run a plain 256 MiB copy and a few H psi steps of the headline workload only "
                          "(for counter collection)")
@@ -431,6 +434,12 @@ def main():
         out["batched_kpoints"] = batched_times(B, W, dev, 3, prob=prob, dp=dp, x=x64)
     del y64
     torch.cuda.synchronize()
+    if not args.no_davidson:
+        log("C3 Davidson iterations")
+        B.set_tuning()
+        out["davidson_c3"] = davidson_iteration_times(B, dev, prob, dp, iters=2)
+        if tuning:
+            B.set_tuning(**tuning["fp64"])
     if not args.no_cpu:
         log("CPU baseline (oracle)")
         out["cpu_baseline"] = cpu_baseline(prob)
@@ -441,7 +450,7 @@ def main():
 
     if not args.no_c4:
         log("C4 mixed precision")
-        out["mixed_precision_c4"] = c4_times(B, W, dev)
+        out["mixed_precision_c4"] = c4_times(B, W, dev, davidson=not args.no_davidson)
     if not args.no_c2:
         log("C2 legs")
         c2 = W.make_problem("C2")
@@ -460,9 +469,14 @@ def main():
         if not args.no_davidson:
             log("C2 Davidson")
             out["davidson"] = davidson_times(B, W, dev)
+            log("C5 Davidson")
+            out["davidson_c5"] = davidson_times(B, W, dev, "C5", modes=(("fp64", 0), ("mixed_bf16", 2)))
         if not args.no_cg:
             log("C2 CG")
             out["cg_vs_davidson"] = cg_times(B, W, dev, out.get("davidson"))
+    if args.c4_davidson:
+        log("C4 Davidson to 1e-8")
+        out["davidson_c4"] = davidson_times(B, W, dev, "C4", max_iter=300, modes=(("fp64", 0), ("mixed_bf16", 2)))
     if not args.no_backward:
         log("C5 adjoint")
         out["backward"] = backward_times(B, W, dev, max(5, args.steps // 4))
@@ -566,7 +580,7 @@ def density_times(B, W, dev, prob, dp, x, steps):
     return res
 
 
-def c4_times(B, W, dev):
+def c4_times(B, W, dev, davidson=True):
     """The mixed-precision workload (C4: cubic a=30 bohr, ecutwfc=50 Ry, 128^3, 161,235 PW,
     256 atoms x 9 projectors (s+p+d, full D blocks), 1024 bands): one H psi in FP64, FP32,
     MIXED_FP32 (FP32 transforms and GEMMs, complex128 psi) and MIXED_BF16 (FP32 transforms,
@@ -623,6 +637,11 @@ def c4_times(B, W, dev):
             row["speedup_vs_fp64"] = res["fp64"]["ms_per_h_psi"] / ms
         res[name] = row
         del y, yc
+    del ref
+    torch.cuda.synchronize()
+    if davidson:
+        log("C4 Davidson iterations")
+        res["davidson_iterations"] = davidson_iteration_times(B, dev, prob, dp, iters=2)
     return res
 
 
@@ -853,41 +872,64 @@ def cg_times(B, W, dev, dav):
     return res
 
 
-def davidson_times(B, W, dev):
-    """Block Davidson on the benchmark workload to a 1e-8 residual: FP64, and the two mixed
-    modes (reduced-precision phase with FP32 or bf16 products, then FP64 refinement)."""
+def davidson_times(B, W, dev, workload="C2", tol=1e-8, max_iter=200,
+                   modes=(("fp64", 0), ("mixed_fp32", 3), ("mixed_bf16", 2))):
+    """Block Davidson to a `tol` residual: FP64, and the mixed modes (reduced-precision
+    phase with FP32 or bf16 products, then FP64 refinement); eigenvalue differences of
+    each mixed run from the FP64 run of the same GPU (the FP64 Davidson itself is checked
+    against the oracle in the GPU tests)."""
     import torch
-    res = {}
-    prob = W.make_problem("C2")
-    dp = B.DeviceProblem(prob, device=dev)
+    res = {"workload": workload, "tol": tol}
+    prob = W.make_problem(workload)
+    dp = B.DeviceProblem(prob, device=dev, static=True)
     x = torch.from_numpy(prob.psi).to(dev)
     B.apply_h(dp, x)   # plan and work space built outside the timed solves
     torch.cuda.synchronize()
-    for name, prec in (("fp64", B.FP64), ("mixed_fp32", B.MIXED_FP32), ("mixed_bf16", B.MIXED_BF16)):
+    eigs = {}
+    for name, prec in modes:
         x = torch.from_numpy(prob.psi).to(dev)
         torch.cuda.synchronize()
+        log(f"Davidson {workload} {name}")
         t0 = time.perf_counter()
         try:
-            eig, r, its, st = B.davidson(dp, x, tol=1e-8, max_iter=200, precision=prec)
+            eig, r, its, st = B.davidson(dp, x, tol=tol, max_iter=max_iter, precision=prec)
         except B.AbacusPwError as e:
             res[name] = {"error": str(e)}
             continue
         dt = time.perf_counter() - t0
-        res[name] = {"s_per_kpoint": dt / prob.nk, "iterations": int(its[0]), "max_resid": float(r.max()),
-                     "converged": st == 0, "lowest": float(eig[0, 0]), "highest": float(eig[0, -1])}
-        res[name + "_eig"] = eig[0].tolist()
-    if "fp64_eig" in res and "mixed_fp32_eig" in res:
-        res["mixed_vs_fp64_max_eig_diff"] = float(np.max(np.abs(np.array(res["fp64_eig"]) -
-                                                               np.array(res["mixed_fp32_eig"]))))
-        res["mixed_speedup"] = res["fp64"]["s_per_kpoint"] / res["mixed_fp32"]["s_per_kpoint"]
-    if "fp64_eig" in res and "mixed_bf16_eig" in res:
-        res["mixed_bf16_vs_fp64_max_eig_diff"] = float(np.max(np.abs(np.array(res["fp64_eig"]) -
-                                                                    np.array(res["mixed_bf16_eig"]))))
-        res["mixed_bf16_speedup"] = res["fp64"]["s_per_kpoint"] / res["mixed_bf16"]["s_per_kpoint"]
-    for key in ("fp64_eig", "mixed_fp32_eig", "mixed_bf16_eig"):
-        res.pop(key, None)
+        res[name] = {"s_per_kpoint": dt / prob.nk, "iterations": [int(v) for v in its], "max_resid": float(r.max()),
+                     "converged": st == 0, "lowest": float(eig.min()), "highest": float(eig.max())}
+        eigs[name] = eig
+    if "fp64" in eigs:
+        for name in eigs:
+            if name != "fp64":
+                res[name]["max_eig_diff_vs_fp64"] = float(np.max(np.abs(eigs[name] - eigs["fp64"])))
+                res[name]["speedup_vs_fp64"] = res["fp64"]["s_per_kpoint"] / res[name]["s_per_kpoint"]
+    del dp, x
+    B.plan_reset()
     return res
 
+
+def davidson_iteration_times(B, dev, prob, dp, iters=3):
+    """Seconds per Davidson iteration on a large workload, FP64 and MIXED_BF16: the solve is
+    run with max_iter = 0 (Cholesky-QR, H psi and Rayleigh-Ritz of the start) and with
+    max_iter = iters (tol 1e-30, so exactly that many correction steps), and the difference
+    is divided by iters * nk."""
+    import torch
+    out = {"iterations": iters}
+    for name, prec in (("fp64", B.FP64), ("mixed_bf16", B.MIXED_BF16)):
+        t = []
+        for n in (0, iters):
+            x = torch.from_numpy(prob.psi).to(dev)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            B.davidson(dp, x, tol=1e-30, max_iter=n, precision=prec)
+            t.append(time.perf_counter() - t0)
+            del x
+        out[name] = {"s_per_iteration_per_kpoint": (t[1] - t[0]) / (iters * prob.nk),
+                     "s_start_per_kpoint": t[0] / prob.nk}
+        log(f"Davidson iterations {name}: {out[name]}")
+    return out
 
 if __name__ == "__main__":
     main()

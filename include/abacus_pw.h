@@ -150,6 +150,31 @@ int abacus_pw_apply_h(const abacus_pw_problem *p, int precision, int nb, const v
                       void *stream);
 
 /*
+ * H psi with a work space supplied by the caller (the hpsi = H psi of
+ * abacus_pw_apply_h, Sec. III.A / II.A, same results bit for bit).
+ *
+ * abacus_pw_workspace_size builds the problem's plan if it does not exist (it
+ * allocates the plan's tables and its reduced-precision operator copies for
+ * `precision`, and synchronises) and writes to *bytes the work-space size
+ * abacus_pw_apply_h_ws needs for nb bands at that precision: the slab of
+ * grid planes of one band batch at every k-point, the projections and their
+ * split-K partial sums (and the bf16 / FP32 staging of the mixed modes). The
+ * size depends on the tuning knobs (band batch, split-K chunk): query it again
+ * after abacus_pw_set_tuning.
+ *
+ * abacus_pw_apply_h_ws then applies H using `workspace` (device memory of at
+ * least that many bytes, 256-byte aligned, owned by the caller; its contents are
+ * scratch). Once the plan exists, the call allocates nothing, synchronises
+ * nothing and records no memset, so even its first call can be captured in a
+ * HIP graph. Calls sharing one work space must be ordered by the caller.
+ * Errors: those of abacus_pw_apply_h, ENULL_ARG (workspace), EBAD_SHAPE (work space too
+ * small for the current knobs, or misaligned).
+ */
+int abacus_pw_workspace_size(const abacus_pw_problem *p, int precision, int nb, size_t *bytes, void *stream);
+int abacus_pw_apply_h_ws(const abacus_pw_problem *p, int precision, int nb, const void *psi, void *hpsi,
+                         void *workspace, size_t ws_bytes, void *stream);
+
+/*
  * Lowest nb eigenpairs of H at every k-point by band-by-band preconditioned
  * conjugate gradients (the CG figure of Sec. III.B): band i is projected
  * against bands 0..i-1 and normalised, then repeatedly moved along a
@@ -371,10 +396,13 @@ int abacus_pw_profile_read(char *buf, int size);
  *              each band batch's B Q as soon as its local term is done; events order the
  *              two streams and join the second back into the caller's stream before the
  *              call returns, so stream semantics and graph capture are unchanged; 2 one stream
+ * yz_threads   threads per work-group of the compact-row plane kernels (planes too large
+ *              for LDS, one or two work-groups per CU): 256 or 1024 (0 = library default, 1024)
  * Results do not depend on the knobs beyond rounding (the split-K chunk changes the
  * summation grouping of the projections). Returns EBAD_SHAPE for invalid values.
  */
-int abacus_pw_set_tuning(int band_batch, int splitk_chunk, int yz_bands, int x_bands, int yz_mode, int overlap);
+int abacus_pw_set_tuning(int band_batch, int splitk_chunk, int yz_bands, int x_bands, int yz_mode, int overlap,
+                         int yz_threads);
 
 #ifdef __cplusplus
 }

@@ -27,8 +27,10 @@ CANDIDATES = {
     "x_bands": [2, 4, 8],
     "splitk_chunk": [256, 512, 1024],
     "overlap": [1, 2],
+    "yz_threads": [256, 1024],
 }
-DEFAULT = {"band_batch": 0, "splitk_chunk": 0, "yz_bands": 0, "x_bands": 0, "yz_mode": 0, "overlap": 0}
+DEFAULT = {"band_batch": 0, "splitk_chunk": 0, "yz_bands": 0, "x_bands": 0, "yz_mode": 0, "overlap": 0,
+           "yz_threads": 0}
 
 
 def cache_path() -> str:
@@ -42,7 +44,7 @@ def key(dp: B.DeviceProblem, nb: int, precision: int) -> str:
 
 def _apply(cfg):
     B.set_tuning(cfg["band_batch"], cfg["splitk_chunk"], cfg["yz_bands"], cfg["x_bands"], cfg.get("yz_mode", 0),
-                 cfg.get("overlap", 0))
+                 cfg.get("overlap", 0), cfg.get("yz_threads", 0))
 
 
 def _time(dp, x, y, nb, precision, reps, trials=3):

@@ -26,6 +26,7 @@ ERRORS = {
 EXPORTS = ["abacus_pw_apply_h", "abacus_pw_davidson", "abacus_pw_cg", "abacus_pw_apply_h_backward", "abacus_pw_density",
            "abacus_pw_chebyshev", "abacus_pw_chebyshev_coefficients", "abacus_pw_force_nl", "abacus_pw_density_g",
            "abacus_pw_eigh_lowest", "abacus_pw_cholesky",
+           "abacus_pw_workspace_size", "abacus_pw_apply_h_ws",
            "abacus_pw_last_error",
            "abacus_pw_fft_supported", "abacus_pw_plan_reset", "abacus_pw_profile_enable",
            "abacus_pw_profile_read", "abacus_pw_set_tuning"]
@@ -58,22 +59,30 @@ def lib():
             raise RuntimeError(f"{LIB_PATH} is missing: build it with python -m paper_2501_08697_amd.build")
         L = C.CDLL(LIB_PATH)
         P, vp, i, d = C.POINTER(CProblem), C.c_void_p, C.c_int, C.c_double
-        L.abacus_pw_apply_h.argtypes = [P, i, i, vp, vp, vp]
-        L.abacus_pw_apply_h_backward.argtypes = [P, i, i, vp, vp, vp, vp, vp, vp]
-        L.abacus_pw_davidson.argtypes = [P, i, i, vp, vp, d, i, i, vp, vp, vp]
-        L.abacus_pw_density.argtypes = [P, i, i, vp, vp, vp, vp]
-        L.abacus_pw_chebyshev.argtypes = [P, i, i, vp, vp, vp, i, d, d, vp]
-        L.abacus_pw_force_nl.argtypes = [P, i, i, vp, vp, vp, vp]
-        L.abacus_pw_density_g.argtypes = [vp, vp, i, vp, vp, vp]
-        L.abacus_pw_eigh_lowest.argtypes = [i, vp, i, i, vp, vp, i, vp]
-        L.abacus_pw_cholesky.argtypes = [i, vp, i, vp, i, vp]
-        L.abacus_pw_chebyshev_coefficients.argtypes = [i, d, d, d, d, d, vp]
-        L.abacus_pw_cg.argtypes = [P, i, vp, vp, d, i, vp, vp, vp]
-        L.abacus_pw_last_error.argtypes = [C.c_char_p, i]
-        L.abacus_pw_fft_supported.argtypes = [i]
-        L.abacus_pw_profile_enable.argtypes = [i]
-        L.abacus_pw_profile_read.argtypes = [C.c_char_p, i]
-        L.abacus_pw_set_tuning.argtypes = [i, i, i, i, i, i]
+        sigs = {
+            "abacus_pw_apply_h": [P, i, i, vp, vp, vp],
+            "abacus_pw_apply_h_backward": [P, i, i, vp, vp, vp, vp, vp, vp],
+            "abacus_pw_davidson": [P, i, i, vp, vp, d, i, i, vp, vp, vp],
+            "abacus_pw_density": [P, i, i, vp, vp, vp, vp],
+            "abacus_pw_chebyshev": [P, i, i, vp, vp, vp, i, d, d, vp],
+            "abacus_pw_force_nl": [P, i, i, vp, vp, vp, vp],
+            "abacus_pw_density_g": [vp, vp, i, vp, vp, vp],
+            "abacus_pw_workspace_size": [P, i, i, C.POINTER(C.c_size_t), vp],
+            "abacus_pw_apply_h_ws": [P, i, i, vp, vp, vp, C.c_size_t, vp],
+            "abacus_pw_eigh_lowest": [i, vp, i, i, vp, vp, i, vp],
+            "abacus_pw_cholesky": [i, vp, i, vp, i, vp],
+            "abacus_pw_chebyshev_coefficients": [i, d, d, d, d, d, vp],
+            "abacus_pw_cg": [P, i, vp, vp, d, i, vp, vp, vp],
+            "abacus_pw_last_error": [C.c_char_p, i],
+            "abacus_pw_fft_supported": [i],
+            "abacus_pw_profile_enable": [i],
+            "abacus_pw_profile_read": [C.c_char_p, i],
+            "abacus_pw_set_tuning": [i, i, i, i, i, i, i],
+        }
+        for name, sig in sigs.items():
+            # a symbol missing from an older build fails when called, not at load
+            if hasattr(L, name):
+                getattr(L, name).argtypes = sig
         _lib = L
     return _lib
 
@@ -212,6 +221,33 @@ def apply_h(dp: DeviceProblem, psi, precision: int = FP64, nb: int | None = None
     return y
 
 
+def workspace_size(dp: DeviceProblem, precision: int = FP64, nb: int | None = None, stream=None) -> int:
+    """Bytes of work space apply_h_ws needs (builds the plan and the operator copies)."""
+    nb = dp.prob.nb if nb is None else nb
+    out = C.c_size_t(0)
+    cp = dp.c()
+    check(lib().abacus_pw_workspace_size(C.byref(cp), int(precision), int(nb), C.byref(out), _stream(stream)))
+    return int(out.value)
+
+
+def apply_h_ws(dp: DeviceProblem, psi, workspace, precision: int = FP64, nb: int | None = None, out=None,
+               stream=None):
+    """H psi with a caller work space (a uint8 device tensor of workspace_size bytes)."""
+    import torch
+    nb = dp.prob.nb if nb is None else nb
+    dt = _psi_dtype(precision)
+    _dev_tensor(psi, "psi", dt, dp.psi_len(nb))
+    y = torch.empty_like(psi) if out is None else _dev_tensor(out, "out", dt, dp.psi_len(nb), psi.device)
+    if not isinstance(workspace, torch.Tensor) or not workspace.is_cuda or not workspace.is_contiguous():
+        raise AbacusPwError(-2, "workspace must be a contiguous device tensor")
+    dp.check_operator(psi.device)
+    cp = dp.c()
+    check(lib().abacus_pw_apply_h_ws(C.byref(cp), int(precision), int(nb), psi.data_ptr(), y.data_ptr(),
+                                     workspace.data_ptr(), workspace.numel() * workspace.element_size(),
+                                     _stream(stream)))
+    return y
+
+
 def apply_h_backward(dp: DeviceProblem, psi, dy, precision: int = FP64, nb: int | None = None, want=("psi", "v", "d"),
                      stream=None, vloc=None, dmat=None):
     """(grad_psi, grad_vloc, grad_dmat) of L with upstream dy = dL/d(H psi)."""
@@ -270,6 +306,8 @@ def density_g(rho, miller=None, stream=None, out=None):
             raise AbacusPwError(-2, "miller must be [ng][3]")
         ng = int(m.shape[0])
         shape = (ng,)
+        if ng == 0:
+            return torch.empty(0, dtype=torch.complex128, device=rho.device)
     y = (torch.empty(shape, dtype=torch.complex128, device=rho.device) if out is None
          else _dev_tensor(out, "out", torch.complex128, ng, rho.device))
     check(lib().abacus_pw_density_g(fft.ctypes.data, rho.data_ptr(), int(ng), None if m is None else m.data_ptr(),
@@ -388,10 +426,10 @@ def plan_reset():
 
 
 def set_tuning(band_batch: int = 0, splitk_chunk: int = 0, yz_bands: int = 0, x_bands: int = 0, yz_mode: int = 0,
-               overlap: int = 0):
+               overlap: int = 0, yz_threads: int = 0):
     """Process-wide kernel tuning knobs (0 = library default)."""
     check(lib().abacus_pw_set_tuning(int(band_batch), int(splitk_chunk), int(yz_bands), int(x_bands), int(yz_mode),
-                                     int(overlap)))
+                                     int(overlap), int(yz_threads)))
 
 
 def profile_enable(on: bool = True):

@@ -139,10 +139,13 @@ int abacus_pw_plan_reset(void) {
     return guarded([&] { return plan_reset_all(); });
 }
 
-int abacus_pw_set_tuning(int band_batch, int splitk_chunk, int yz_bands, int x_bands, int yz_mode, int overlap) {
+int abacus_pw_set_tuning(int band_batch, int splitk_chunk, int yz_bands, int x_bands, int yz_mode, int overlap,
+                         int yz_threads) {
     if (band_batch < 0 || splitk_chunk < 0 || yz_bands < 0 || x_bands < 0 || yz_mode < 0 || yz_mode > 2 ||
-        overlap < 0 || overlap > 2)
-        return set_error(ABACUS_PW_EBAD_SHAPE, "tuning values must be >= 0 (yz_mode and overlap 0, 1 or 2)");
+        overlap < 0 || overlap > 2 || (yz_threads != 0 && yz_threads != 256 && yz_threads != 1024))
+        return set_error(ABACUS_PW_EBAD_SHAPE,
+                         "tuning values must be >= 0 (yz_mode and overlap 0, 1 or 2; yz_threads 0, 256 or 1024)");
+    g_yz_threads = yz_threads;
     g_yz_mode = yz_mode;
     g_overlap = overlap;
     g_band_batch = band_batch;
@@ -188,6 +191,32 @@ int abacus_pw_apply_h(const abacus_pw_problem *p, int precision, int nb, const v
         std::shared_ptr<Plan> P;
         APW_TRY(get_plan(p, static_cast<hipStream_t>(stream), P));
         return apply_h_all(*p, *P, precision, nb, psi, hpsi, static_cast<hipStream_t>(stream));
+    });
+}
+
+int abacus_pw_workspace_size(const abacus_pw_problem *p, int precision, int nb, size_t *bytes, void *stream) {
+    return guarded([&]() -> int {
+        if (!bytes) return set_error(ABACUS_PW_ENULL_ARG, "bytes is required");
+        if (nb < 1) return set_error(ABACUS_PW_EBAD_SHAPE, "nb must be >= 1");
+        if (precision < 0 || precision > 3) return set_error(ABACUS_PW_EBAD_PRECISION, "unknown precision");
+        std::shared_ptr<Plan> P;
+        APW_TRY(get_plan(p, static_cast<hipStream_t>(stream), P));
+        return apply_h_workspace(*P, precision, nb, bytes);
+    });
+}
+
+int abacus_pw_apply_h_ws(const abacus_pw_problem *p, int precision, int nb, const void *psi, void *hpsi,
+                         void *workspace, size_t ws_bytes, void *stream) {
+    return guarded([&]() -> int {
+        if (!psi || !hpsi || !workspace) return set_error(ABACUS_PW_ENULL_ARG, "psi, hpsi and workspace are required");
+        if (psi == hpsi) return set_error(ABACUS_PW_EBAD_SHAPE, "hpsi must not alias psi");
+        if (nb < 1) return set_error(ABACUS_PW_EBAD_SHAPE, "nb must be >= 1");
+        if (precision < 0 || precision > 3) return set_error(ABACUS_PW_EBAD_PRECISION, "unknown precision");
+        if (reinterpret_cast<uintptr_t>(workspace) % 256 != 0)
+            return set_error(ABACUS_PW_EBAD_SHAPE, "workspace must be 256-byte aligned");
+        std::shared_ptr<Plan> P;
+        APW_TRY(get_plan(p, static_cast<hipStream_t>(stream), P));
+        return apply_h_all(*p, *P, precision, nb, psi, hpsi, static_cast<hipStream_t>(stream), workspace, ws_bytes);
     });
 }
 

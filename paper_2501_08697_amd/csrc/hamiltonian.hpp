@@ -14,12 +14,23 @@ int operator_copies(const abacus_pw_problem &p, Plan &P, bool need_v32, bool nee
 int apply_h_k(const abacus_pw_problem &p, Plan &P, int k, int prec, int nb, const void *psi, void *hpsi,
               hipStream_t st, bool refresh_copies = true);
 
-// hpsi = H psi for nb bands at the k-points [k0, k1) (psi starts at k0's block).
+// Per-call work buffers of H psi: slab, Q, split-K partials, bf16 psi, bf16 Q, FP32 psi.
+constexpr int kHWorkParts = 6;
+
+// hpsi = H psi for nb bands at the k-points [k0, k1) (psi starts at k0's block). The work
+// buffers come from the plan (grown as needed) unless ws (ws_bytes) is given, in which case
+// they are carved from it and nothing is allocated.
 int apply_h_range(const abacus_pw_problem &p, Plan &P, int k0, int k1, int prec, int nb, const void *psi, void *hpsi,
-                  hipStream_t st, bool refresh_copies);
+                  hipStream_t st, bool refresh_copies, void *ws = nullptr, size_t ws_bytes = 0);
 
 // hpsi = H psi for nb bands at every k-point (packed [k][nb][npw_k]).
-int apply_h_all(const abacus_pw_problem &p, Plan &P, int prec, int nb, const void *psi, void *hpsi, hipStream_t st);
+int apply_h_all(const abacus_pw_problem &p, Plan &P, int prec, int nb, const void *psi, void *hpsi, hipStream_t st,
+                void *ws = nullptr, size_t ws_bytes = 0);
+
+// Bytes of caller work space apply_h_all needs for (prec, nb) with the current knobs; allocates
+// the plan's operator copies for prec (and the side stream when the overlap knob is on) so a
+// later call with that work space allocates nothing.
+int apply_h_workspace(Plan &P, int prec, int nb, size_t *bytes);
 
 // Adjoint of apply_h_all (abacus_pw_apply_h_backward).
 int apply_h_backward_all(const abacus_pw_problem &p, Plan &P, int prec, int nb, const void *psi, const void *dy,

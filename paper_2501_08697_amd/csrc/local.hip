@@ -328,8 +328,8 @@ __global__ __launch_bounds__((yz_threads<N, T>())) void k_yz_fwd(const cx<T> *__
 // for higher occupancy): only the nr rows of the plane that hold sphere columns
 // are kept in LDS (rows[r][j3], r = position in the plane's row list); the y
 // transforms run through an N2 x C chunk buffer, C consecutive j3 at a time.
-template <int N, typename T, typename TIN>
-__global__ __launch_bounds__(256) void k_yz_inv_c(const cx<TIN> *__restrict__ psi_all, const KDesc *__restrict__ kd,
+template <int N, typename T, typename TIN, int NT>
+__global__ __launch_bounds__(NT) void k_yz_inv_c(const cx<TIN> *__restrict__ psi_all, const KDesc *__restrict__ kd,
                                                   BatchArgs ba, const cx<T> *__restrict__ tw_g,
                                                   cx<T> *__restrict__ slab, int nslab, int bpw, int rows_max, int C) {
     KDesc D;
@@ -381,8 +381,8 @@ __global__ __launch_bounds__(256) void k_yz_inv_c(const cx<TIN> *__restrict__ ps
     }
 }
 
-template <int N, typename T, typename TIO>
-__global__ __launch_bounds__(256) void k_yz_fwd_c(const cx<T> *__restrict__ slab, int nslab,
+template <int N, typename T, typename TIO, int NT>
+__global__ __launch_bounds__(NT) void k_yz_fwd_c(const cx<T> *__restrict__ slab, int nslab,
                                                   const KDesc *__restrict__ kd, BatchArgs ba,
                                                   const cx<T> *__restrict__ tw_g, const cx<TIO> *__restrict__ psi_all,
                                                   cx<TIO> *__restrict__ hpsi_all, double inv_n, int bpw, int rows_max,
@@ -673,26 +673,32 @@ static int launch_yz(bool inverse, const Plan &P, int k0, int nkb, const BatchAr
     const dim3 grid(P.nslab, nkb * ceil_div(ba.bbt, bpw));
     if (compact) {
         const size_t lds = compact_lds<N, T>(P.max_rows, Cc);
+        // threads per work-group: the compact planes hold one or two work-groups per
+        // CU, so more waves per group hide more of the memory latency
+        const bool wide = g_yz_threads != 256;   // default 1024: measured 1.5x faster at 128^3 FP64
+        auto inv = wide ? k_yz_inv_c<N, T, TIO, 1024> : k_yz_inv_c<N, T, TIO, 256>;
+        auto fwd = wide ? k_yz_fwd_c<N, T, TIO, 1024> : k_yz_fwd_c<N, T, TIO, 256>;
+        const dim3 block(wide ? 1024 : 256);
         if (inverse) {
-            static bool once = false;
-            if (!once) {
-                APW_TRY(allow_lds(k_yz_inv_c<N, T, TIO>, kLdsLimit));
-                once = true;
+            static bool once[2] = {false, false};
+            if (!once[wide]) {
+                APW_TRY(allow_lds(inv, kLdsLimit));
+                once[wide] = true;
             }
             KernelTimer kt("yz_inv", st);
-            hipLaunchKernelGGL((k_yz_inv_c<N, T, TIO>), grid, dim3(256), lds, st, static_cast<const cx<TIO> *>(psi),
-                               kd, ba, tw, static_cast<cx<T> *>(slab), P.nslab, bpw, P.max_rows, Cc);
+            hipLaunchKernelGGL(inv, grid, block, lds, st, static_cast<const cx<TIO> *>(psi), kd, ba, tw,
+                               static_cast<cx<T> *>(slab), P.nslab, bpw, P.max_rows, Cc);
             return check_launch("yz_inv_c");
         }
-        static bool once = false;
-        if (!once) {
-            APW_TRY(allow_lds(k_yz_fwd_c<N, T, TIO>, kLdsLimit));
-            once = true;
+        static bool once[2] = {false, false};
+        if (!once[wide]) {
+            APW_TRY(allow_lds(fwd, kLdsLimit));
+            once[wide] = true;
         }
         KernelTimer kt("yz_fwd", st);
-        hipLaunchKernelGGL((k_yz_fwd_c<N, T, TIO>), grid, dim3(256), lds, st, static_cast<const cx<T> *>(slab), P.nslab,
-                           kd, ba, tw, static_cast<const cx<TIO> *>(psi), static_cast<cx<TIO> *>(hpsi),
-                           1.0 / (double)P.N, bpw, P.max_rows, Cc);
+        hipLaunchKernelGGL(fwd, grid, block, lds, st, static_cast<const cx<T> *>(slab), P.nslab, kd, ba, tw,
+                           static_cast<const cx<TIO> *>(psi), static_cast<cx<TIO> *>(hpsi), 1.0 / (double)P.N, bpw,
+                           P.max_rows, Cc);
         return check_launch("yz_fwd_c");
     }
     if (inverse) {

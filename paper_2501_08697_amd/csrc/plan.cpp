@@ -23,6 +23,7 @@ int g_yz_bands = 0;
 int g_x_bands = 0;
 int g_yz_mode = 0;
 int g_overlap = 0;
+int g_yz_threads = 0;
 
 DeviceBuffer::~DeviceBuffer() {
     if (ptr) (void)hipFree(ptr);

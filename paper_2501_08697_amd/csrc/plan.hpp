@@ -117,6 +117,7 @@ extern int g_yz_bands;      // bands per y-z plane work-group
 extern int g_x_bands;       // bands per x-pass work-group
 extern int g_yz_mode;       // plane kernels: 0 auto, 1 full plane in LDS, 2 compact rows
 extern int g_overlap;       // projector GEMMs beside the local term: 0 default (off), 1 on, 2 off
+extern int g_yz_threads;    // threads per work-group of the compact-row plane kernels: 0 default, 256 or 1024
 
 // Looks up or builds the plan for a problem (validates it on build; the
 // operator checks read V and D on `st`, after the caller's earlier work on it).

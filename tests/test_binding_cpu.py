@@ -120,11 +120,13 @@ def test_error_message_is_set(prob):
 
 
 def test_tuning_rejects_negative():
-    assert code_name(B.lib().abacus_pw_set_tuning(-1, 0, 0, 0, 0, 0)) == "EBAD_SHAPE"
-    assert code_name(B.lib().abacus_pw_set_tuning(0, 0, 0, -2, 0, 0)) == "EBAD_SHAPE"
-    assert code_name(B.lib().abacus_pw_set_tuning(0, 0, 0, 0, 3, 0)) == "EBAD_SHAPE"
-    assert code_name(B.lib().abacus_pw_set_tuning(0, 0, 0, 0, 0, 3)) == "EBAD_SHAPE"
-    assert B.lib().abacus_pw_set_tuning(0, 0, 0, 0, 0, 0) == 0
+    assert code_name(B.lib().abacus_pw_set_tuning(-1, 0, 0, 0, 0, 0, 0)) == "EBAD_SHAPE"
+    assert code_name(B.lib().abacus_pw_set_tuning(0, 0, 0, -2, 0, 0, 0)) == "EBAD_SHAPE"
+    assert code_name(B.lib().abacus_pw_set_tuning(0, 0, 0, 0, 3, 0, 0)) == "EBAD_SHAPE"
+    assert code_name(B.lib().abacus_pw_set_tuning(0, 0, 0, 0, 0, 3, 0)) == "EBAD_SHAPE"
+    assert code_name(B.lib().abacus_pw_set_tuning(0, 0, 0, 0, 0, 0, 512)) == "EBAD_SHAPE"
+    assert B.lib().abacus_pw_set_tuning(0, 0, 0, 0, 0, 0, 1024) == 0
+    assert B.lib().abacus_pw_set_tuning(0, 0, 0, 0, 0, 0, 0) == 0
 
 
 def test_density_rejects_before_device_access(prob):
@@ -228,3 +230,15 @@ def test_density_g_rejects_before_device_access():
     assert code_name(L.abacus_pw_density_g(ok.ctypes.data, FAKE, -1, FAKE, FAKE, None)) == "EBAD_SHAPE"
     assert code_name(L.abacus_pw_density_g(None, FAKE, 1, FAKE, FAKE, None)) == "ENULL_ARG"
     assert code_name(L.abacus_pw_density_g(ok.ctypes.data, None, 1, FAKE, FAKE, None)) == "ENULL_ARG"
+
+
+def test_workspace_entry_points_reject_before_device_access(prob):
+    f = Fake(prob)
+    L = B.lib()
+    out = C.c_size_t(0)
+    assert code_name(L.abacus_pw_workspace_size(C.byref(f.s), 0, 1, None, None)) == "ENULL_ARG"
+    assert code_name(L.abacus_pw_workspace_size(C.byref(f.s), 0, 0, C.byref(out), None)) == "EBAD_SHAPE"
+    assert code_name(L.abacus_pw_workspace_size(C.byref(f.s), 9, 1, C.byref(out), None)) == "EBAD_PRECISION"
+    assert code_name(L.abacus_pw_apply_h_ws(C.byref(f.s), 0, 1, FAKE, FAKE + 64, None, 0, None)) == "ENULL_ARG"
+    assert code_name(L.abacus_pw_apply_h_ws(C.byref(f.s), 0, 1, FAKE, FAKE, FAKE, 1 << 20, None)) == "EBAD_SHAPE"
+    assert code_name(L.abacus_pw_apply_h_ws(C.byref(f.s), 0, 1, FAKE, FAKE + 64, FAKE + 8, 1 << 20, None)) == "EBAD_SHAPE"
