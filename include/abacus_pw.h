@@ -313,6 +313,22 @@ int abacus_pw_density(const abacus_pw_problem *p, int precision, int nb, const v
 int abacus_pw_density_g(const int *fft, const double *rho, int ng, const int *miller_g, void *rhog, void *stream);
 
 /*
+ * abacus_pw_density_g for callers that cannot allocate device memory: code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc. Same arguments, kernels and results as abacus_pw_density_g; with a
+ * G list the work grid is a fixed device array of the library (2,097,152
+ * complex128 points = 32 MiB, the 128^3 grid, one copy per device, held until
+ * the process ends) instead of an allocated one. This entry point calls no
+ * hipMalloc or hipFree. Every call on a device shares that device's array and
+ * leaves its contents behind: calls that overlap on one device (different
+ * streams or threads) race and must be ordered by the caller.
+ * Errors: as abacus_pw_density_g, plus EBAD_SHAPE for a G list on a grid of more
+ * than 2,097,152 points.
+ */
+int abacus_pw_density_g_noalloc(const int *fft, const double *rho, int ng, const int *miller_g, void *rhog,
+                                void *stream);
+
+/*
  * Nonlocal (Kleinman-Bylander) force on every atom, the derivative of the
  * projector energy with respect to the atomic positions (Sec. III.A). With the
  * projectors carrying the structure factor exp(-i (k+G).tau_a):

@@ -26,7 +26,7 @@ ERRORS = {
 EXPORTS = ["abacus_pw_apply_h", "abacus_pw_davidson", "abacus_pw_cg", "abacus_pw_apply_h_backward", "abacus_pw_density",
            "abacus_pw_chebyshev", "abacus_pw_chebyshev_coefficients", "abacus_pw_force_nl", "abacus_pw_density_g",
            "abacus_pw_eigh_lowest", "abacus_pw_cholesky",
-           "abacus_pw_workspace_size", "abacus_pw_apply_h_ws",
+           "abacus_pw_workspace_size", "abacus_pw_apply_h_ws", "abacus_pw_density_g_noalloc",
            "abacus_pw_last_error",
            "abacus_pw_fft_supported", "abacus_pw_plan_reset", "abacus_pw_profile_enable",
            "abacus_pw_profile_read", "abacus_pw_set_tuning"]
@@ -67,6 +67,7 @@ def lib():
             "abacus_pw_chebyshev": [P, i, i, vp, vp, vp, i, d, d, vp],
             "abacus_pw_force_nl": [P, i, i, vp, vp, vp, vp],
             "abacus_pw_density_g": [vp, vp, i, vp, vp, vp],
+            "abacus_pw_density_g_noalloc": [vp, vp, i, vp, vp, vp],
             "abacus_pw_workspace_size": [P, i, i, C.POINTER(C.c_size_t), vp],
             "abacus_pw_apply_h_ws": [P, i, i, vp, vp, vp, C.c_size_t, vp],
             "abacus_pw_eigh_lowest": [i, vp, i, i, vp, vp, i, vp],

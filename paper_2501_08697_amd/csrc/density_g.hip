@@ -171,6 +171,31 @@ constexpr int kMaxDevicesDG = 64;
 std::mutex g_dg_mu;
 DeviceBuffer g_dg_work[kMaxDevicesDG];
 
+// Fixed work grid of abacus_pw_density_g_noalloc: the largest grid the library
+// transforms (128^3 points, 32 MiB of complex128), a copy on every device the
+// library runs on, held until the process ends. In host code `scratch` names a
+// host-side stand-in: its device address comes from hipGetSymbolAddress, taken
+// once per device (with that device current) and kept in g_na_ptr.
+constexpr int64_t kNoAllocMaxPoints = 128 * 128 * 128;
+static __device__ __align__(256) z64 scratch[kNoAllocMaxPoints];
+std::mutex g_na_mu;
+void *g_na_ptr[kMaxDevicesDG] = {};
+
+int noalloc_work(z64 **out) {
+    int dev = 0;
+    APW_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevicesDG) return set_error(ABACUS_PW_EINTERNAL, "device index out of range");
+    std::lock_guard<std::mutex> l(g_na_mu);
+    if (!g_na_ptr[dev]) {
+        void *ptr = nullptr;
+        APW_HIP(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+        if (!ptr) return set_error(ABACUS_PW_EHIP, "no device address for the fixed work grid");
+        g_na_ptr[dev] = ptr;
+    }
+    *out = static_cast<z64 *>(g_na_ptr[dev]);
+    return ABACUS_PW_OK;
+}
+
 }  // namespace
 
 }  // namespace apw
@@ -197,6 +222,23 @@ extern "C" int abacus_pw_density_g(const int *fft, const double *rho, int ng, co
             }
             work = g_dg_work[dev].as<z64>();
         }
+        APW_TRY(transform(fft, rho, work, st));
+        return gather(fft, work, ng, miller_g, rhog, st);
+    } catch (...) {
+        return set_error(ABACUS_PW_EINTERNAL, "internal error");
+    }
+}
+
+extern "C" int abacus_pw_density_g_noalloc(const int *fft, const double *rho, int ng, const int *miller_g, void *rhog,
+                                           void *stream) {
+    try {
+        APW_TRY(check_args(fft, rho, ng, miller_g, rhog));
+        hipStream_t st = static_cast<hipStream_t>(stream);
+        if (!miller_g) return transform(fft, rho, static_cast<z64 *>(rhog), st);
+        if ((int64_t)fft[0] * fft[1] * fft[2] > kNoAllocMaxPoints)
+            return set_error(ABACUS_PW_EBAD_SHAPE, "grid larger than the fixed work grid (2,097,152 points)");
+        z64 *work = nullptr;
+        APW_TRY(noalloc_work(&work));
         APW_TRY(transform(fft, rho, work, st));
         return gather(fft, work, ng, miller_g, rhog, st);
     } catch (...) {
