@@ -27,7 +27,7 @@ CANDIDATES = {
     "x_bands": [2, 4, 8],
     "splitk_chunk": [256, 512, 1024],
     "overlap": [1, 2],
-    "yz_threads": [256, 1024],
+    "yz_threads": [256, 512, 1024],
 }
 DEFAULT = {"band_batch": 0, "splitk_chunk": 0, "yz_bands": 0, "x_bands": 0, "yz_mode": 0, "overlap": 0,
            "yz_threads": 0}

@@ -142,9 +142,9 @@ int abacus_pw_plan_reset(void) {
 int abacus_pw_set_tuning(int band_batch, int splitk_chunk, int yz_bands, int x_bands, int yz_mode, int overlap,
                          int yz_threads) {
     if (band_batch < 0 || splitk_chunk < 0 || yz_bands < 0 || x_bands < 0 || yz_mode < 0 || yz_mode > 2 ||
-        overlap < 0 || overlap > 2 || (yz_threads != 0 && yz_threads != 256 && yz_threads != 1024))
+        overlap < 0 || overlap > 2 || (yz_threads != 0 && yz_threads != 256 && yz_threads != 512 && yz_threads != 1024))
         return set_error(ABACUS_PW_EBAD_SHAPE,
-                         "tuning values must be >= 0 (yz_mode and overlap 0, 1 or 2; yz_threads 0, 256 or 1024)");
+                         "tuning values must be >= 0 (yz_mode and overlap 0, 1 or 2; yz_threads 0, 256, 512 or 1024)");
     g_yz_threads = yz_threads;
     g_yz_mode = yz_mode;
     g_overlap = overlap;

@@ -345,20 +345,28 @@ __global__ void k_grad_d(int nb, int M, const cx<T> *__restrict__ P, const cx<T>
 }
 
 // ------------------------------------------------------------ launchers ----
+// Default K chunk: at least 512 work-groups, chunks of at most 1024 (a K chunk of
+// A and B read by every tile of the chunk stays in the caches, where one long K
+// range per tile streams A once per column of tiles from HBM: at 2304 x 1024 x
+// 161,235 the projection read 13.7x its operands with one split, measured with
+// FETCH_SIZE), but no more splits than keep the partial sums under kPartCap bytes.
+constexpr size_t kPartCap = size_t(1) << 30;
 static int splits_for(int M, int N, int K, int chunk_hint, int *chunk) {
     const int tiles = ceil_div(M, TM) * ceil_div(N, TN);
     int c = chunk_hint > 0 ? chunk_hint : 0;
     if (c <= 0) {
         const int want = std::max(1, 512 / std::max(1, tiles));
-        c = std::max(256, ceil_div(K, want));
+        c = std::min(1024, std::max(256, ceil_div(K, want)));
+        const int64_t max_splits = std::max<int64_t>(1, (int64_t)(kPartCap / ((size_t)M * N * 16)));
+        c = std::max<int64_t>(c, ceil_div64(K, max_splits));
     }
     c = ceil_div(c, KT) * KT;
     *chunk = c;
     return std::max(1, ceil_div(K, c));
 }
 
-// Upper bound over every K' <= K: with a chunk hint the split count grows with K;
-// without one it never exceeds the work-group target 512 / tiles.
+// Upper bound over every K' <= K: the split count grows with K up to the cap (with
+// a chunk hint without one).
 size_t gemm_cn_part_bytes(int M, int N, int K, int elem_bytes, int chunk_hint) {
     int c;
     int ns = splits_for(M, N, K, chunk_hint, &c);

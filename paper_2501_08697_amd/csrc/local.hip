@@ -51,7 +51,8 @@ __device__ __forceinline__ void batch_block(const KDesc *kd, const BatchArgs &ba
 }
 
 constexpr int kMaxT3 = 32;     // widest j3 tile of the x pass
-constexpr int kXBands = 4;     // bands per x-pass work-group
+constexpr int kXBands = 4;     // bands per x-pass work-group (FP32)
+constexpr int kXBands64 = 8;   // FP64: V is read once per work-group, and 8 bands measured fastest at 72^3 - 128^3
 // Threads of a y-z plane work-group. An FP64 plane in LDS allows one group per
 // CU, so up to N = 72 it runs 16 waves; larger planes need more registers per
 // thread than 1024 threads leave (128 VGPRs), and FP32 planes fit three groups
@@ -328,10 +329,14 @@ __global__ __launch_bounds__((yz_threads<N, T>())) void k_yz_fwd(const cx<T> *__
 // for higher occupancy): only the nr rows of the plane that hold sphere columns
 // are kept in LDS (rows[r][j3], r = position in the plane's row list); the y
 // transforms run through an N2 x C chunk buffer, C consecutive j3 at a time.
+// These planes leave room for one work-group per CU, so nothing else on the CU
+// covers a global load's latency: both kernels keep the next loads in flight
+// behind the current work (the next band's sphere values in the inverse pass;
+// the next chunk's slab values and this band's psi in the forward pass).
 template <int N, typename T, typename TIN, int NT>
 __global__ __launch_bounds__(NT) void k_yz_inv_c(const cx<TIN> *__restrict__ psi_all, const KDesc *__restrict__ kd,
-                                                  BatchArgs ba, const cx<T> *__restrict__ tw_g,
-                                                  cx<T> *__restrict__ slab, int nslab, int bpw, int rows_max, int C) {
+                                                 BatchArgs ba, const cx<T> *__restrict__ tw_g,
+                                                 cx<T> *__restrict__ slab, int nslab, int bpw, int rows_max, int C) {
     KDesc D;
     int kk, b0, b1;
     int s;
@@ -346,33 +351,59 @@ __global__ __launch_bounds__(NT) void k_yz_inv_c(const cx<TIN> *__restrict__ psi
     cx<T> *ybuf = rows + rows_max * N;
     cx<T> *tw = ybuf + N * C;
     int *map = reinterpret_cast<int *>(tw + N);
-    const int tid = threadIdx.x, nthr = blockDim.x;
+    const int tid = threadIdx.x;
     const int r0 = row_off[s], nr = row_off[s + 1] - r0;
     const int p0 = pt_off[s], p1 = pt_off[s + 1];
-    for (int i = tid; i < N; i += nthr) tw[i] = tw_g[i];
-    for (int r = tid; r < nr; r += nthr) map[row_list[r0 + r]] = r;
+    for (int i = tid; i < N; i += NT) tw[i] = tw_g[i];
+    for (int r = tid; r < nr; r += NT) map[row_list[r0 + r]] = r;
+    // the plane's first MAXP * NT sphere points: psi index and compact-row LDS position,
+    // held in registers for every band (point p1 - 1 stands in for unused slots); fewer
+    // per thread at 1024 threads, whose FP64 transforms leave no registers for more
+    constexpr int MAXP = NT >= 1024 ? (sizeof(T) == 8 && N >= 128 ? 0 : 1) : 4;
+    int gc[MAXP > 0 ? MAXP : 1], pos[MAXP > 0 ? MAXP : 1];
+#pragma unroll
+    for (int q = 0; q < MAXP; ++q) {
+        const int p = p1 > p0 ? min(p0 + tid + q * NT, p1 - 1) : 0;
+        gc[q] = pt_g[p];
+        pos[q] = pt_pos[p];
+    }
+    cx<TIN> pre[MAXP > 0 ? MAXP : 1];
+#pragma unroll
+    for (int q = 0; q < MAXP; ++q) pre[q] = psi[b0 * ldpsi + gc[q]];
     __syncthreads();
+#pragma unroll
+    for (int q = 0; q < MAXP; ++q) {
+        const int slot = pos[q] / N;
+        pos[q] = p0 + tid + q * NT < p1 ? map[slot] * N + (pos[q] - slot * N) : -1;
+    }
     for (int b = b0; b < b1; ++b) {
-        for (int i = tid; i < nr * N; i += nthr) rows[i] = czero<T>();
+        for (int i = tid; i < nr * N; i += NT) rows[i] = czero<T>();
         __syncthreads();
-        for (int p = p0 + tid; p < p1; p += nthr) {
-            const int pos = pt_pos[p], slot = pos / N;
-            rows[map[slot] * N + (pos - slot * N)] = cvt<T>(psi[b * ldpsi + pt_g[p]]);
+#pragma unroll
+        for (int q = 0; q < MAXP; ++q)
+            if (pos[q] >= 0) rows[pos[q]] = cvt<T>(pre[q]);
+        for (int p = p0 + MAXP * NT + tid; p < p1; p += NT) {
+            const int ps = pt_pos[p], slot = ps / N;
+            rows[map[slot] * N + (ps - slot * N)] = cvt<T>(psi[b * ldpsi + pt_g[p]]);
         }
         __syncthreads();
+        if (b + 1 < b1) {
+#pragma unroll
+            for (int q = 0; q < MAXP; ++q) pre[q] = psi[(b + 1) * ldpsi + gc[q]];
+        }
         lds_fft<N, +1, false>(rows, nr, [](int l) { return l * N; }, 1, tw);
         cx<T> *out = slab + ((int64_t)b * nslab + s) * (int64_t)(N * N);
         for (int c0 = 0; c0 < N; c0 += C) {
             const int w = min(C, N - c0);
-            for (int i = tid; i < N * w; i += nthr) ybuf[(i / w) * C + (i % w)] = czero<T>();
+            for (int i = tid; i < N * w; i += NT) ybuf[(i / w) * C + (i % w)] = czero<T>();
             __syncthreads();
-            for (int i = tid; i < nr * w; i += nthr) {
+            for (int i = tid; i < nr * w; i += NT) {
                 const int r = i / w, c = i - r * w;
                 ybuf[row_list[r0 + r] * C + c] = rows[r * N + c0 + c];
             }
             __syncthreads();
             lds_fft<N, +1, true>(ybuf, w, [](int l) { return l; }, C, tw);
-            for (int i = tid; i < N * w; i += nthr) {
+            for (int i = tid; i < N * w; i += NT) {
                 const int j2 = i / w, c = i - j2 * w;
                 out[j2 * N + c0 + c] = ybuf[j2 * C + c];
             }
@@ -383,10 +414,10 @@ __global__ __launch_bounds__(NT) void k_yz_inv_c(const cx<TIN> *__restrict__ psi
 
 template <int N, typename T, typename TIO, int NT>
 __global__ __launch_bounds__(NT) void k_yz_fwd_c(const cx<T> *__restrict__ slab, int nslab,
-                                                  const KDesc *__restrict__ kd, BatchArgs ba,
-                                                  const cx<T> *__restrict__ tw_g, const cx<TIO> *__restrict__ psi_all,
-                                                  cx<TIO> *__restrict__ hpsi_all, double inv_n, int bpw, int rows_max,
-                                                  int C) {
+                                                 const KDesc *__restrict__ kd, BatchArgs ba,
+                                                 const cx<T> *__restrict__ tw_g, const cx<TIO> *__restrict__ psi_all,
+                                                 cx<TIO> *__restrict__ hpsi_all, double inv_n, int bpw, int rows_max,
+                                                 int C) {
     KDesc D;
     int kk, b0, b1;
     int s;
@@ -404,35 +435,92 @@ __global__ __launch_bounds__(NT) void k_yz_fwd_c(const cx<T> *__restrict__ slab,
     cx<T> *ybuf = rows + rows_max * N;
     cx<T> *tw = ybuf + N * C;
     int *map = reinterpret_cast<int *>(tw + N);
-    const int tid = threadIdx.x, nthr = blockDim.x;
+    const int tid = threadIdx.x;
     const int r0 = row_off[s], nr = row_off[s + 1] - r0;
     const int p0 = pt_off[s], p1 = pt_off[s + 1];
     const TIO sc = static_cast<TIO>(inv_n);
-    for (int i = tid; i < N; i += nthr) tw[i] = tw_g[i];
-    for (int r = tid; r < nr; r += nthr) map[row_list[r0 + r]] = r;
+    for (int i = tid; i < N; i += NT) tw[i] = tw_g[i];
+    for (int r = tid; r < nr; r += NT) map[row_list[r0 + r]] = r;
+    // slab values of one chunk (N2 x w): the first MAXQ per thread are fetched ahead
+    constexpr int MAXQ = NT >= 1024 ? 1 : 4;
+    const int nchunk = (N + C - 1) / C;
+    cx<T> pre[MAXQ];
+    // slab index of the thread's q-th value of chunk ci of band b (-1: none); a plain
+    // function of registers, so the prefetch array stays in registers
+    auto src_of = [=](int b, int ci, int q) -> int64_t {
+        const int c0 = ci * C, w = min(C, N - c0), i = tid + q * NT;
+        if (i >= N * w) return -1;
+        const int j2 = i / w, c = i - j2 * w;
+        return ((int64_t)b * nslab + s) * (int64_t)(N * N) + j2 * N + c0 + c;
+    };
+#pragma unroll
+    for (int q = 0; q < MAXQ; ++q) {
+        const int64_t o = src_of(b0, 0, q);
+        pre[q] = o >= 0 ? slab[o] : czero<T>();
+    }
+    // the plane's first MAXP * NT sphere points: psi index and compact-row position
+    constexpr int MAXP = NT >= 1024 ? 1 : 4;
+    int gi[MAXP], pos[MAXP];
+#pragma unroll
+    for (int q = 0; q < MAXP; ++q) {
+        const int p = p1 > p0 ? min(p0 + tid + q * NT, p1 - 1) : 0;
+        gi[q] = pt_g[p];
+        pos[q] = pt_pos[p];
+    }
     __syncthreads();
+#pragma unroll
+    for (int q = 0; q < MAXP; ++q) {
+        const int slot = pos[q] / N;
+        pos[q] = p0 + tid + q * NT < p1 ? map[slot] * N + (pos[q] - slot * N) : -1;
+    }
     for (int b = b0; b < b1; ++b) {
+        const cx<TIO> *x = psi + b * ld;
+        cx<TIO> *y = hpsi + b * ld;
         const cx<T> *in = slab + ((int64_t)b * nslab + s) * (int64_t)(N * N);
-        for (int c0 = 0; c0 < N; c0 += C) {
-            const int w = min(C, N - c0);
-            for (int i = tid; i < N * w; i += nthr) {
+        for (int ci = 0; ci < nchunk; ++ci) {
+            const int c0 = ci * C, w = min(C, N - c0);
+#pragma unroll
+            for (int q = 0; q < MAXQ; ++q) {
+                const int i = tid + q * NT;
+                if (i < N * w) ybuf[(i / w) * C + (i % w)] = pre[q];
+            }
+            for (int i = tid + MAXQ * NT; i < N * w; i += NT) {
                 const int j2 = i / w, c = i - j2 * w;
                 ybuf[j2 * C + c] = in[j2 * N + c0 + c];
             }
             __syncthreads();
+            // the next chunk (or the next band's first chunk) is fetched behind this one
+            const int nb_ = ci + 1 < nchunk ? b : b + 1, nc_ = ci + 1 < nchunk ? ci + 1 : 0;
+#pragma unroll
+            for (int q = 0; q < MAXQ; ++q) {
+                const int64_t o = nb_ < b1 ? src_of(nb_, nc_, q) : -1;
+                pre[q] = o >= 0 ? slab[o] : czero<T>();
+            }
             lds_fft<N, -1, true>(ybuf, w, [](int l) { return l; }, C, tw);
-            for (int i = tid; i < nr * w; i += nthr) {
+            for (int i = tid; i < nr * w; i += NT) {
                 const int r = i / w, c = i - r * w;
                 rows[r * N + c0 + c] = ybuf[row_list[r0 + r] * C + c];
             }
             __syncthreads();
         }
+        // this band's psi and |k+G|^2 at the thread's points, fetched behind the z transforms
+        cx<TIO> xq[MAXP];
+        TIO kq[MAXP];
+#pragma unroll
+        for (int q = 0; q < MAXP; ++q) {
+            xq[q] = x[gi[q]];
+            kq[q] = static_cast<TIO>(kin[gi[q]]);
+        }
         lds_fft<N, -1, false>(rows, nr, [](int l) { return l * N; }, 1, tw);
-        const cx<TIO> *x = psi + b * ld;
-        cx<TIO> *y = hpsi + b * ld;
-        for (int p = p0 + tid; p < p1; p += nthr) {
-            const int g = pt_g[p], pos = pt_pos[p], slot = pos / N;
-            const cx<TIO> v = cvt<TIO>(rows[map[slot] * N + (pos - slot * N)]);
+#pragma unroll
+        for (int q = 0; q < MAXP; ++q)
+            if (pos[q] >= 0) {
+                const cx<TIO> v = cvt<TIO>(rows[pos[q]]);
+                y[gi[q]] = cx<TIO>{kq[q] * xq[q].re + sc * v.re, kq[q] * xq[q].im + sc * v.im};
+            }
+        for (int p = p0 + MAXP * NT + tid; p < p1; p += NT) {
+            const int g = pt_g[p], ps = pt_pos[p], slot = ps / N;
+            const cx<TIO> v = cvt<TIO>(rows[map[slot] * N + (ps - slot * N)]);
             const TIO kg = static_cast<TIO>(kin[g]);
             const cx<TIO> xg = x[g];
             y[g] = cx<TIO>{kg * xg.re + sc * v.re, kg * xg.im + sc * v.im};
@@ -675,25 +763,26 @@ static int launch_yz(bool inverse, const Plan &P, int k0, int nkb, const BatchAr
         const size_t lds = compact_lds<N, T>(P.max_rows, Cc);
         // threads per work-group: the compact planes hold one or two work-groups per
         // CU, so more waves per group hide more of the memory latency
-        const bool wide = g_yz_threads != 256;   // default 1024: measured 1.5x faster at 128^3 FP64
-        auto inv = wide ? k_yz_inv_c<N, T, TIO, 1024> : k_yz_inv_c<N, T, TIO, 256>;
-        auto fwd = wide ? k_yz_fwd_c<N, T, TIO, 1024> : k_yz_fwd_c<N, T, TIO, 256>;
-        const dim3 block(wide ? 1024 : 256);
+        const int nt = g_yz_threads > 0 ? g_yz_threads : 1024;   // 1024 measured 1.5x faster than 256 at 128^3 FP64
+        const int sel = nt == 256 ? 0 : (nt == 512 ? 1 : 2);
+        auto inv = sel == 0 ? k_yz_inv_c<N, T, TIO, 256> : (sel == 1 ? k_yz_inv_c<N, T, TIO, 512> : k_yz_inv_c<N, T, TIO, 1024>);
+        auto fwd = sel == 0 ? k_yz_fwd_c<N, T, TIO, 256> : (sel == 1 ? k_yz_fwd_c<N, T, TIO, 512> : k_yz_fwd_c<N, T, TIO, 1024>);
+        const dim3 block(nt);
         if (inverse) {
-            static bool once[2] = {false, false};
-            if (!once[wide]) {
+            static bool once[3] = {false, false, false};
+            if (!once[sel]) {
                 APW_TRY(allow_lds(inv, kLdsLimit));
-                once[wide] = true;
+                once[sel] = true;
             }
             KernelTimer kt("yz_inv", st);
             hipLaunchKernelGGL(inv, grid, block, lds, st, static_cast<const cx<TIO> *>(psi), kd, ba, tw,
                                static_cast<cx<T> *>(slab), P.nslab, bpw, P.max_rows, Cc);
             return check_launch("yz_inv_c");
         }
-        static bool once[2] = {false, false};
-        if (!once[wide]) {
+        static bool once[3] = {false, false, false};
+        if (!once[sel]) {
             APW_TRY(allow_lds(fwd, kLdsLimit));
-            once[wide] = true;
+            once[sel] = true;
         }
         KernelTimer kt("yz_fwd", st);
         hipLaunchKernelGGL(fwd, grid, block, lds, st, static_cast<const cx<T> *>(slab), P.nslab, kd, ba, tw,
@@ -745,7 +834,7 @@ static int launch_x(const Plan &P, const void *vloc, void *slab, int nbands, hip
         once = true;
     }
     const cx<T> *tw = static_cast<const cx<T> *>(sizeof(T) == 8 ? P.tw64[0] : P.tw32[0]);
-    const int bpw = g_x_bands > 0 ? g_x_bands : kXBands;
+    const int bpw = g_x_bands > 0 ? g_x_bands : (sizeof(T) == 8 ? kXBands64 : kXBands);
     dim3 grid(P.N2 * nt3, ceil_div(nbands, bpw));
     KernelTimer kt("xpass", st);
     hipLaunchKernelGGL((k_xpass<N1, T, T>), grid, dim3(256), lds, st, static_cast<cx<T> *>(slab), P.nslab, P.N2,

@@ -124,7 +124,7 @@ def test_tuning_rejects_negative():
     assert code_name(B.lib().abacus_pw_set_tuning(0, 0, 0, -2, 0, 0, 0)) == "EBAD_SHAPE"
     assert code_name(B.lib().abacus_pw_set_tuning(0, 0, 0, 0, 3, 0, 0)) == "EBAD_SHAPE"
     assert code_name(B.lib().abacus_pw_set_tuning(0, 0, 0, 0, 0, 3, 0)) == "EBAD_SHAPE"
-    assert code_name(B.lib().abacus_pw_set_tuning(0, 0, 0, 0, 0, 0, 512)) == "EBAD_SHAPE"
+    assert code_name(B.lib().abacus_pw_set_tuning(0, 0, 0, 0, 0, 0, 300)) == "EBAD_SHAPE"
     assert B.lib().abacus_pw_set_tuning(0, 0, 0, 0, 0, 0, 1024) == 0
     assert B.lib().abacus_pw_set_tuning(0, 0, 0, 0, 0, 0, 0) == 0
 
