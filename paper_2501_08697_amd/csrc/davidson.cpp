@@ -38,8 +38,38 @@ namespace {
 
 struct Buffers {
     DeviceBuffer V, HV, Xc, Wc, R, Y, Hs, Hw, coef, C, G, Linv, part, theta, rn2, ek, n0, n1, act, idx, info, heev, bfs,
-        chol;
+        chol, info2;
 };
+
+// Pinned host staging for the index lists uploaded each iteration: the copies are
+// enqueued without waiting, and a list is rewritten only after the next read-back
+// (which waits for the stream) has ordered it behind its copy.
+struct HostLists {
+    int *act = nullptr, *keep = nullptr, *idx = nullptr;
+    double *theta = nullptr;
+    int n = 0;
+    ~HostLists() {
+        if (act) (void)hipHostFree(act);
+    }
+    int ensure(int m) {
+        if (m <= n) return ABACUS_PW_OK;
+        if (act) APW_HIP(hipHostFree(act));
+        void *p = nullptr;
+        APW_HIP(hipHostMalloc(&p, (sizeof(int) * 3 + sizeof(double)) * (size_t)m, hipHostMallocDefault));
+        act = static_cast<int *>(p);
+        keep = act + m;
+        idx = keep + m;
+        theta = reinterpret_cast<double *>(idx + m);
+        n = m;
+        return ABACUS_PW_OK;
+    }
+};
+
+// Enqueue an upload from pinned host memory (no wait).
+int h2d_async(void *dst, const void *src, size_t bytes, hipStream_t st) {
+    APW_HIP(hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, st));
+    return ABACUS_PW_OK;
+}
 
 int d2h(void *dst, const void *src, size_t bytes, hipStream_t st) {
     APW_HIP(hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToHost, st));
@@ -56,6 +86,15 @@ int h2d(void *dst, const void *src, size_t bytes, hipStream_t st) {
 int d2d(void *dst, const void *src, size_t bytes, hipStream_t st) {
     APW_HIP(hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToDevice, st));
     return ABACUS_PW_OK;
+}
+
+// One Cholesky-QR pass without a wait: Y = L^{-1} T with G = T^H T = L L^H; the
+// pivot status goes to *info_dev (the caller reads it later). T is unchanged.
+int cholqr_pass_async(int m, int npw, const z64 *T, z64 *Y, Buffers &b, int *info_dev, hipStream_t st) {
+    z64 *G = b.G.as<z64>(), *Linv = b.Linv.as<z64>();
+    APW_TRY(gemm_cn(0, m, m, npw, T, npw, T, npw, G, m, 1.0, 0.0, b.part.ptr, 0, st));
+    APW_TRY(potrf_inv(m, G, m, Linv, m, info_dev, b.chol.ptr, st));
+    return gemm_nn(0, m, npw, m, Linv, m, T, npw, Y, npw, 1.0, 0.0, st);
 }
 
 // Orthonormalise the m rows of T (length npw) by `passes` Cholesky-QR passes;
@@ -117,9 +156,9 @@ struct Result {
 // corrections are orthogonalised against them together with the basis that
 // follows them in V, and Rayleigh-Ritz keeps the lowest nA = nb - nl pairs.
 // The output merges both sets in ascending order of their Ritz values.
-int davidson_k(const abacus_pw_problem &p, Plan &P, int k, int hprec, int nb, z64 *X, Buffers &b, double tol,
-               int max_iter, int ndim, int stagnation, std::vector<double> &theta_h, std::vector<double> &rn_h,
-               Result &res, hipStream_t st) {
+int davidson_k(const abacus_pw_problem &p, Plan &P, int k, int hprec, int nb, z64 *X, Buffers &b, HostLists &hl,
+               double tol, int max_iter, int ndim, int stagnation, std::vector<double> &theta_h,
+               std::vector<double> &rn_h, Result &res, hipStream_t st) {
     const int npw = P.k[k].npw, nmax = ndim * nb;
     const double *kin = P.k[k].kin;
     if (nmax > kMaxSub) return set_error(ABACUS_PW_EBAD_SHAPE, "ndim * nb exceeds the device eigensolver limit (4096)");
@@ -142,11 +181,13 @@ int davidson_k(const abacus_pw_problem &p, Plan &P, int k, int hprec, int nb, z6
     APW_TRY(b.theta.ensure(sizeof(double) * nmax));
     APW_TRY(b.rn2.ensure(sizeof(double) * nb));
     APW_TRY(b.ek.ensure(sizeof(double) * nb));
-    APW_TRY(b.n0.ensure(sizeof(double) * nb));
+    APW_TRY(b.n0.ensure(sizeof(double) * 2 * nb + 64));   // norms before, then after the projection
     APW_TRY(b.n1.ensure(sizeof(double) * nb));
     APW_TRY(b.act.ensure(sizeof(int) * nb));
     APW_TRY(b.idx.ensure(sizeof(int) * nb));
     APW_TRY(b.info.ensure(sizeof(int)));
+    APW_TRY(b.info2.ensure(sizeof(int)));
+    APW_TRY(hl.ensure(nb));
     APW_TRY(b.heev.ensure(heev_scratch_bytes(nmax)));
     APW_TRY(b.chol.ensure(potrf_scratch_bytes(nb)));
     z64 *V = b.V.as<z64>(), *HV = b.HV.as<z64>(), *Xc = b.Xc.as<z64>(), *Wc = b.Wc.as<z64>(), *R = b.R.as<z64>();
@@ -186,10 +227,21 @@ int davidson_k(const abacus_pw_problem &p, Plan &P, int k, int hprec, int nb, z6
     double best = INFINITY;
     int since_best = 0;
     res = Result{};
+    double *nrm0 = b.n0.as<double>(), *nrm1 = nrm0 + nb;   // correction norms before / after the projection
+    bool check_info2 = false;   // the last iteration's second Cholesky-QR pass has a status to read
+    // Host crossings per iteration: one read of the residual norms (with the status of the
+    // previous second Cholesky-QR pass), one read of the correction norms with the status of
+    // the first pass, which runs before that read on every correction; uploads of index lists
+    // are enqueued from pinned memory without a wait.
     for (;;) {
         z64 *Vb = V + (size_t)nl * npw;
         APW_TRY(dav_resid(nA, npw, Xc, Wc, theta, kin, R, b.rn2.as<double>(), b.ek.as<double>(), st));
-        APW_TRY(d2h(rn2.data(), b.rn2.ptr, sizeof(double) * nA, st));
+        int info2 = 0;
+        APW_HIP(hipMemcpyAsync(rn2.data(), b.rn2.ptr, sizeof(double) * nA, hipMemcpyDeviceToHost, st));
+        if (check_info2) APW_HIP(hipMemcpyAsync(&info2, b.info2.ptr, sizeof(int), hipMemcpyDeviceToHost, st));
+        APW_HIP(hipStreamSynchronize(st));
+        if (info2 != 0)
+            return set_error(ABACUS_PW_ECHOLESKY, "second Cholesky-QR pass of the corrections not positive definite");
         act.clear();
         conv.clear();
         double worst = 0.0;
@@ -212,7 +264,8 @@ int davidson_k(const abacus_pw_problem &p, Plan &P, int k, int hprec, int nb, z6
             }
         }
         int m = (int)act.size();
-        APW_TRY(h2d(b.act.ptr, act.data(), sizeof(int) * m, st));
+        std::copy(act.begin(), act.end(), hl.act);
+        APW_TRY(h2d_async(b.act.ptr, hl.act, sizeof(int) * m, st));
         const bool restart = nbasis + m > nmax;
         z64 *T;
         if (restart && !conv.empty()) {
@@ -220,7 +273,8 @@ int davidson_k(const abacus_pw_problem &p, Plan &P, int k, int hprec, int nb, z6
             // active ones become the new basis
             const int nc = (int)conv.size();
             APW_TRY(dav_precond(m, npw, b.act.as<int>(), R, kin, b.ek.as<double>(), Y, st));
-            APW_TRY(h2d(b.idx.ptr, conv.data(), sizeof(int) * nc, st));
+            std::copy(conv.begin(), conv.end(), hl.idx);
+            APW_TRY(h2d_async(b.idx.ptr, hl.idx, sizeof(int) * nc, st));
             APW_TRY(dav_gather_rows(nc, npw, b.idx.as<int>(), Xc, Vb, st));
             Vb = V + (size_t)(nl + nc) * npw;
             APW_TRY(dav_gather_rows(m, npw, b.act.as<int>(), Xc, Vb, st));
@@ -232,9 +286,8 @@ int davidson_k(const abacus_pw_problem &p, Plan &P, int k, int hprec, int nb, z6
                 thL.push_back(thA[i]);
                 rnL.push_back(std::sqrt(rn2[i]));
             }
-            std::vector<double> th_new(m);
-            for (int i = 0; i < m; ++i) th_new[i] = thA[act[i]];
-            APW_TRY(h2d(theta, th_new.data(), sizeof(double) * m, st));
+            for (int i = 0; i < m; ++i) hl.theta[i] = thA[act[i]];
+            APW_TRY(h2d_async(theta, hl.theta, sizeof(double) * m, st));
             nl += nc;
             nA = m;
             nbasis = m;
@@ -253,27 +306,44 @@ int davidson_k(const abacus_pw_problem &p, Plan &P, int k, int hprec, int nb, z6
         }
         z64 *HT = HV + (size_t)nbasis * npw;
         const int north = nl + nbasis;   // locked rows and basis, contiguous in V
-        APW_TRY(dav_row_norm2(m, npw, T, b.n0.as<double>(), st));
+        APW_TRY(dav_row_norm2(m, npw, T, nrm0, st));
         for (int pass = 0; pass < 2; ++pass) {
             APW_TRY(gemm_cn(0, north, m, npw, V, npw, T, npw, C, north, 1.0, 0.0, b.part.ptr, 0, st));
             APW_TRY(gemm_nn(0, m, npw, north, C, north, V, npw, T, npw, -1.0, 1.0, st));
         }
-        APW_TRY(dav_row_norm2(m, npw, T, b.n1.as<double>(), st));
-        APW_TRY(d2h(n0.data(), b.n0.ptr, sizeof(double) * m, st));
-        APW_TRY(d2h(n1.data(), b.n1.ptr, sizeof(double) * m, st));
+        APW_TRY(dav_row_norm2(m, npw, T, nrm1, st));
+        // first Cholesky-QR pass on every correction (Y = L^{-1} T), before the drop test
+        // is known: it is kept when nothing is dropped and its pivots are positive
+        APW_TRY(cholqr_pass_async(m, npw, T, Y, b, b.info.as<int>(), st));
+        int info1 = 0;
+        APW_HIP(hipMemcpyAsync(n0.data(), nrm0, sizeof(double) * m, hipMemcpyDeviceToHost, st));
+        APW_HIP(hipMemcpyAsync(n1.data(), nrm1, sizeof(double) * m, hipMemcpyDeviceToHost, st));
+        APW_HIP(hipMemcpyAsync(&info1, b.info.ptr, sizeof(int), hipMemcpyDeviceToHost, st));
+        APW_HIP(hipStreamSynchronize(st));
         keep.clear();
         for (int i = 0; i < m; ++i)
             if (std::sqrt(n1[i]) >= 1e-10 * std::sqrt(n0[i])) keep.push_back(i);
+        check_info2 = false;
         if ((int)keep.size() < m) {
+            // corrections fell into the basis: drop them, then Cholesky-QR on the rest
             if (!keep.empty()) {
-                APW_TRY(h2d(b.act.ptr, keep.data(), sizeof(int) * keep.size(), st));
+                std::copy(keep.begin(), keep.end(), hl.keep);
+                APW_TRY(h2d_async(b.act.ptr, hl.keep, sizeof(int) * keep.size(), st));
                 APW_TRY(dav_gather_rows((int)keep.size(), npw, b.act.as<int>(), T, Y, st));
                 APW_TRY(d2d(T, Y, vb * keep.size(), st));
             }
             m = (int)keep.size();
+            if (m == 0) break;
+            APW_TRY(cholqr_rows(m, npw, T, Y, b, 2, st));
+        } else if (info1 != 0) {
+            // not positive definite: Cholesky-QR with the shifted retry
+            APW_TRY(cholqr_rows(m, npw, T, Y, b, 2, st));
+        } else {
+            APW_TRY(d2d(T, Y, vb * m, st));
+            APW_TRY(cholqr_pass_async(m, npw, T, Y, b, b.info2.as<int>(), st));
+            APW_TRY(d2d(T, Y, vb * m, st));
+            check_info2 = true;
         }
-        if (m == 0) break;
-        APW_TRY(cholqr_rows(m, npw, T, Y, b, 2, st));
         APW_TRY(apply_h_k(p, P, k, hprec, m, T, HT, st, false));
         const int n = nbasis + m;
         APW_TRY(project(n, m, Vb, HT, C, n));
@@ -293,6 +363,12 @@ int davidson_k(const abacus_pw_problem &p, Plan &P, int k, int hprec, int nb, z6
     for (int n = 0; n < nA; ++n) {
         theta_h.push_back(thA[n]);
         rn_h.push_back(std::sqrt(rn2[n]));
+    }
+    if (check_info2) {
+        int info2 = 0;
+        APW_TRY(d2h(&info2, b.info2.ptr, sizeof(int), st));
+        if (info2 != 0)
+            return set_error(ABACUS_PW_ECHOLESKY, "second Cholesky-QR pass of the corrections not positive definite");
     }
     if (nl == 0) {
         APW_TRY(d2d(X, Xc, vb * nb, st));
@@ -321,6 +397,7 @@ int davidson_all(const abacus_pw_problem &p, Plan &P, int prec, int nb, void *ps
                  int max_iter, int ndim, int *iters, double *resid, hipStream_t st) {
     APW_TRY(local_supported(P, 0));   // the refinement phase always runs FP64 transforms
     Buffers b;
+    HostLists hl;
     bool all = true;
     std::vector<double> th, rn;
     // operator copies once per solve (the reduced-precision phase reads them)
@@ -333,10 +410,10 @@ int davidson_all(const abacus_pw_problem &p, Plan &P, int prec, int nb, void *ps
         if (prec != ABACUS_PW_FP64) {
             // reduced-precision phase: stop at its noise floor (FP32 ~1e-5, BF16 projectors ~1e-3) or on stagnation
             const double tol_a = std::max(tol, prec == ABACUS_PW_MIXED_BF16 ? 1e-3 : 1e-5);
-            APW_TRY(davidson_k(p, P, k, prec, nb, X, b, tol_a, max_iter, ndim, 3, th, rn, r, st));
+            APW_TRY(davidson_k(p, P, k, prec, nb, X, b, hl, tol_a, max_iter, ndim, 3, th, rn, r, st));
             total += r.iters;
         }
-        APW_TRY(davidson_k(p, P, k, ABACUS_PW_FP64, nb, X, b, tol, std::max(0, max_iter - total), ndim, 0, th, rn, r,
+        APW_TRY(davidson_k(p, P, k, ABACUS_PW_FP64, nb, X, b, hl, tol, std::max(0, max_iter - total), ndim, 0, th, rn, r,
                            st));
         total += r.iters;
         all = all && r.converged;
