@@ -329,6 +329,13 @@ __global__ __launch_bounds__((yz_threads<N, T>())) void k_yz_fwd(const cx<T> *__
 // for higher occupancy): only the nr rows of the plane that hold sphere columns
 // are kept in LDS (rows[r][j3], r = position in the plane's row list); the y
 // transforms run through an N2 x C chunk buffer, C consecutive j3 at a time.
+// The two phases of each chunk's y transform are written out here rather than
+// taken from lds_fft, so that they read and write the compact rows and the slab
+// themselves: the inverse's first phase takes its inputs from the compact rows
+// (slots without a row are zero) and its second phase stores the natural-order
+// outputs to the slab; the forward's second phase writes the slots that have a
+// row straight into the compact rows. A chunk then costs two (inverse) or three
+// (forward) barriers instead of five and four, and no zero or copy passes.
 // These planes leave room for one work-group per CU, so nothing else on the CU
 // covers a global load's latency: both kernels keep the next loads in flight
 // behind the current work (the next band's sphere values in the inverse pass;
@@ -354,7 +361,12 @@ __global__ __launch_bounds__(NT) void k_yz_inv_c(const cx<TIN> *__restrict__ psi
     const int tid = threadIdx.x;
     const int r0 = row_off[s], nr = row_off[s + 1] - r0;
     const int p0 = pt_off[s], p1 = pt_off[s + 1];
-    for (int i = tid; i < N; i += NT) tw[i] = tw_g[i];
+    constexpr int A = LdsSplit<N>::A, B = LdsSplit<N>::B;
+    for (int i = tid; i < N; i += NT) {
+        tw[i] = tw_g[i];
+        map[i] = -1;
+    }
+    __syncthreads();
     for (int r = tid; r < nr; r += NT) map[row_list[r0 + r]] = r;
     // the plane's first MAXP * NT sphere points: psi index and compact-row LDS position,
     // held in registers for every band (point p1 - 1 stands in for unused slots); fewer
@@ -395,17 +407,31 @@ __global__ __launch_bounds__(NT) void k_yz_inv_c(const cx<TIN> *__restrict__ psi
         cx<T> *out = slab + ((int64_t)b * nslab + s) * (int64_t)(N * N);
         for (int c0 = 0; c0 < N; c0 += C) {
             const int w = min(C, N - c0);
-            for (int i = tid; i < N * w; i += NT) ybuf[(i / w) * C + (i % w)] = czero<T>();
-            __syncthreads();
-            for (int i = tid; i < nr * w; i += NT) {
-                const int r = i / w, c = i - r * w;
-                ybuf[row_list[r0 + r] * C + c] = rows[r * N + c0 + c];
+            // phase 1, task (c, ka): slots B ka + kb of column c0 + c from the compact rows,
+            // inverse DFT_B, twiddle, to ybuf slots B ka + jb
+            for (int t = tid; t < w * A; t += NT) {
+                const int c = t % w, ka = t / w;
+                cx<T> z[B];
+#pragma unroll
+                for (int kb = 0; kb < B; ++kb) {
+                    const int r = map[B * ka + kb];
+                    z[kb] = r >= 0 ? rows[r * N + c0 + c] : czero<T>();
+                }
+                RegDft<B, +1, T>::run(z);
+                ybuf[(B * ka) * C + c] = z[0];
+#pragma unroll
+                for (int jb = 1; jb < B; ++jb) ybuf[(B * ka + jb) * C + c] = cmul(z[jb], tw[jb * A + ka]);
             }
             __syncthreads();
-            lds_fft<N, +1, true>(ybuf, w, [](int l) { return l; }, C, tw);
-            for (int i = tid; i < N * w; i += NT) {
-                const int j2 = i / w, c = i - j2 * w;
-                out[j2 * N + c0 + c] = ybuf[j2 * C + c];
+            // phase 2, task (c, jb): inverse DFT_A of slots B ka + jb; j2 = jb + B ja goes to the slab
+            for (int t = tid; t < w * B; t += NT) {
+                const int c = t % w, jb = t / w;
+                cx<T> a[A];
+#pragma unroll
+                for (int ka = 0; ka < A; ++ka) a[ka] = ybuf[(B * ka + jb) * C + c];
+                RegDft<A, +1, T>::run(a);
+#pragma unroll
+                for (int ja = 0; ja < A; ++ja) out[(jb + B * ja) * N + c0 + c] = a[ja];
             }
             __syncthreads();
         }
@@ -439,7 +465,12 @@ __global__ __launch_bounds__(NT) void k_yz_fwd_c(const cx<T> *__restrict__ slab,
     const int r0 = row_off[s], nr = row_off[s + 1] - r0;
     const int p0 = pt_off[s], p1 = pt_off[s + 1];
     const TIO sc = static_cast<TIO>(inv_n);
-    for (int i = tid; i < N; i += NT) tw[i] = tw_g[i];
+    constexpr int A = LdsSplit<N>::A, B = LdsSplit<N>::B;
+    for (int i = tid; i < N; i += NT) {
+        tw[i] = tw_g[i];
+        map[i] = -1;
+    }
+    __syncthreads();
     for (int r = tid; r < nr; r += NT) map[row_list[r0 + r]] = r;
     // slab values of one chunk (N2 x w): the first MAXQ per thread are fetched ahead
     constexpr int MAXQ = NT >= 1024 ? 1 : 4;
@@ -496,10 +527,31 @@ __global__ __launch_bounds__(NT) void k_yz_fwd_c(const cx<T> *__restrict__ slab,
                 const int64_t o = nb_ < b1 ? src_of(nb_, nc_, q) : -1;
                 pre[q] = o >= 0 ? slab[o] : czero<T>();
             }
-            lds_fft<N, -1, true>(ybuf, w, [](int l) { return l; }, C, tw);
-            for (int i = tid; i < nr * w; i += NT) {
-                const int r = i / w, c = i - r * w;
-                rows[r * N + c0 + c] = ybuf[row_list[r0 + r] * C + c];
+            // phase 1, task (c, jb): forward DFT_A of natural j2 = jb + B ja, twiddle, back in place
+            for (int t = tid; t < w * B; t += NT) {
+                const int c = t % w, jb = t / w;
+                cx<T> a[A];
+#pragma unroll
+                for (int ja = 0; ja < A; ++ja) a[ja] = ybuf[(jb + B * ja) * C + c];
+                RegDft<A, -1, T>::run(a);
+                ybuf[jb * C + c] = a[0];
+#pragma unroll
+                for (int ka = 1; ka < A; ++ka) ybuf[(jb + B * ka) * C + c] = cmulc(a[ka], tw[jb * A + ka]);
+            }
+            __syncthreads();
+            // phase 2, task (c, ka): forward DFT_B of slots B ka + jb; output slot B ka + kb
+            // goes to its compact row when the plane has one there
+            for (int t = tid; t < w * A; t += NT) {
+                const int c = t % w, ka = t / w;
+                cx<T> z[B];
+#pragma unroll
+                for (int jb = 0; jb < B; ++jb) z[jb] = ybuf[(B * ka + jb) * C + c];
+                RegDft<B, -1, T>::run(z);
+#pragma unroll
+                for (int kb = 0; kb < B; ++kb) {
+                    const int r = map[B * ka + kb];
+                    if (r >= 0) rows[r * N + c0 + c] = z[kb];
+                }
             }
             __syncthreads();
         }
