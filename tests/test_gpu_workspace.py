@@ -28,7 +28,13 @@ def problem(seed):
 def test_first_call_captured_in_graph(prec):
     b = B()
     b.set_tuning()
-    p = problem(40 + prec)    # a geometry no earlier call has seen: a new plan
+    # Every seed has the same cell, cutoff and k-points, so the same sphere: without a reset
+    # a cached plan could be found again (its key holds the Miller array's address, which a
+    # new host array may reuse), together with reduced-precision operator copies that a
+    # static operator at a reused device address would leave stale. The first call of the
+    # test must build its plan.
+    b.plan_reset()
+    p = problem(40 + prec)
     dp = b.DeviceProblem(p, static=True)
     x = torch.from_numpy(p.psi).cuda()
     if prec == b.FP32:
