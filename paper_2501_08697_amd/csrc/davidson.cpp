@@ -208,6 +208,21 @@ int davidson_k(const abacus_pw_problem &p, Plan &P, int k, int hprec, int nb, z6
             return gemm_cn_bf16_of_f64(M, N, npw, A, npw, B, npw, Cout, ldc, b.bfs.ptr, st);
         return gemm_cn_f32_of_f64(M, N, npw, A, npw, B, npw, Cout, ldc, 1.0, 0.0, b.part.ptr, 0, st);
     };
+    // basis products of the iteration (the projection against the basis, the basis
+    // updates to the Ritz vectors): FP64, or in the bf16 phase (which stops at a residual
+    // of 1e-3) FP32 products on the FP64 vectors with FP64 results. The FP32 phase, which
+    // goes to 1e-5, keeps them FP64: with FP32 products there its iterations to 1e-8 at
+    // 72^3 rose from 39 to 68. Cholesky-QR and the residuals stay FP64.
+    const bool low = hprec == ABACUS_PW_MIXED_BF16;
+    auto basis_cn = [&](int M, int N, const z64 *A, const z64 *B, z64 *Cout, int ldc) -> int {
+        return low ? gemm_cn_f32_of_f64(M, N, npw, A, npw, B, npw, Cout, ldc, 1.0, 0.0, b.part.ptr, 0, st)
+                   : gemm_cn(0, M, N, npw, A, npw, B, npw, Cout, ldc, 1.0, 0.0, b.part.ptr, 0, st);
+    };
+    auto basis_nn = [&](int M, int K, const z64 *A, int lda, const z64 *B, z64 *Cout, double alpha,
+                        double beta) -> int {
+        return low ? gemm_nn_f32_of_f64(M, npw, K, A, lda, B, npw, Cout, npw, alpha, beta, st)
+                   : gemm_nn(0, M, npw, K, A, lda, B, npw, Cout, npw, alpha, beta, st);
+    };
     APW_TRY(project(nb, nb, Xc, Wc, C, nb));
     APW_TRY(dav_hs_append(0, nb, C, nb, Hs, nmax, st));
     APW_TRY(dav_copy_block(nb, Hs, nmax, Hw, nmax, st));
@@ -308,8 +323,8 @@ int davidson_k(const abacus_pw_problem &p, Plan &P, int k, int hprec, int nb, z6
         const int north = nl + nbasis;   // locked rows and basis, contiguous in V
         APW_TRY(dav_row_norm2(m, npw, T, nrm0, st));
         for (int pass = 0; pass < 2; ++pass) {
-            APW_TRY(gemm_cn(0, north, m, npw, V, npw, T, npw, C, north, 1.0, 0.0, b.part.ptr, 0, st));
-            APW_TRY(gemm_nn(0, m, npw, north, C, north, V, npw, T, npw, -1.0, 1.0, st));
+            APW_TRY(basis_cn(north, m, V, T, C, north));
+            APW_TRY(basis_nn(m, north, C, north, V, T, -1.0, 1.0));
         }
         APW_TRY(dav_row_norm2(m, npw, T, nrm1, st));
         // first Cholesky-QR pass on every correction (Y = L^{-1} T), before the drop test
@@ -350,8 +365,8 @@ int davidson_k(const abacus_pw_problem &p, Plan &P, int k, int hprec, int nb, z6
         APW_TRY(dav_hs_append(nbasis, m, C, n, Hs, nmax, st));
         APW_TRY(dav_copy_block(n, Hs, nmax, Hw, nmax, st));
         APW_TRY(rayleigh_ritz(n, nA, nmax, b, &rc, st));
-        APW_TRY(gemm_nn(0, nA, npw, n, rc, nmax, Vb, npw, Xc, npw, 1.0, 0.0, st));
-        APW_TRY(gemm_nn(0, nA, npw, n, rc, nmax, HV, npw, Wc, npw, 1.0, 0.0, st));
+        APW_TRY(basis_nn(nA, n, rc, nmax, Vb, Xc, 1.0, 0.0));
+        APW_TRY(basis_nn(nA, n, rc, nmax, HV, Wc, 1.0, 0.0));
         nbasis = n;
         ++res.iters;
     }

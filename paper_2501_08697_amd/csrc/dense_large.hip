@@ -70,6 +70,7 @@ struct TrdArgs {
     z64 *tau;
     z64 *Vr;      // [n][n] reflector rows (zero outside k+1 .. n-1)
     z64 *PX, *PY; // [n][2 kPL]
+    z64 *PXc;     // [2 kPL][n]: PX by columns, so that reads over rows are coalesced
     z64 *vbuf;    // [n] current reflector, contiguous
     z64 *y;       // [n] tau (A22 v - ...) of the current column
     z64 *s;       // [2 kPL]: W^H v then V^H v
@@ -113,19 +114,41 @@ __global__ __launch_bounds__(kColThreads) void k_trd_col(TrdArgs a, int k0, int 
             wl[i] = w;
             a.PX[(int64_t)i * 2 * kPL + kPL + (c - 1)] = w;
             a.PY[(int64_t)i * 2 * kPL + (c - 1)] = w;
+            a.PXc[(int64_t)(kPL + c - 1) * n + i] = w;
         }
         __syncthreads();
     }
     if (mode == 1) return;
+    // row k of the panel (V then W), the same for every row below
+    __shared__ z64 pk[2 * kPL];
+    if (tid < c) {
+        pk[tid] = a.PXc[(int64_t)tid * n + k];
+        pk[kPL + tid] = tid == c - 1 ? wl[k] : a.PXc[(int64_t)(kPL + tid) * n + k];
+    }
+    __syncthreads();
     // column k, rows k .. n-1: conj(row k of A) minus the panel's updates of columns q < c
+    // (the panel read by columns: consecutive threads, consecutive rows)
+    // Eight columns' values are loaded before any is used, so their latencies overlap; the
+    // index is clamped to c - 1 (a valid address) and values beyond c are not used. Column
+    // c - 1 of W is being written by this kernel: its values come from wl instead.
     for (int i = k + tid; i < n; i += kColThreads) {
         z64 x = zc(a.A[(int64_t)k * a.ld + i]);
-        for (int q = 0; q < c; ++q) {
-            const z64 *px_i = a.PX + (int64_t)i * 2 * kPL, *px_k = a.PX + (int64_t)k * 2 * kPL;
-            const z64 vi = px_i[q], vk = px_k[q];
-            const z64 wi = q == c - 1 ? wl[i] : px_i[kPL + q];
-            const z64 wk = q == c - 1 ? wl[k] : px_k[kPL + q];
-            x = x - cmulc(vi, wk) - cmulc(wi, vk);   // v_i conj(w_k) + w_i conj(v_k)
+        for (int q0 = 0; q0 < c; q0 += 8) {
+            z64 vi[8], wi[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int q = min(q0 + u, c - 1);
+                vi[u] = a.PXc[(int64_t)q * n + i];
+                wi[u] = a.PXc[(int64_t)(kPL + q) * n + i];
+            }
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int q = q0 + u;
+                if (q < c) {
+                    const z64 w = q == c - 1 ? wl[i] : wi[u];
+                    x = x - cmulc(vi[u], pk[kPL + q]) - cmulc(w, pk[q]);   // v_i conj(w_k) + w_i conj(v_k)
+                }
+            }
         }
         al[i] = x;
     }
@@ -160,6 +183,7 @@ __global__ __launch_bounds__(kColThreads) void k_trd_col(TrdArgs a, int k0, int 
             al[i] = v;   // al now holds v
             a.PX[(int64_t)i * 2 * kPL + c] = v;
             a.PY[(int64_t)i * 2 * kPL + kPL + c] = v;
+            a.PXc[(int64_t)c * n + i] = v;
         }
     }
     __syncthreads();
@@ -167,12 +191,24 @@ __global__ __launch_bounds__(kColThreads) void k_trd_col(TrdArgs a, int k0, int 
     for (int q2 = wv; q2 < 2 * c; q2 += nwv) {
         const bool isw = q2 < c;
         const int q = isw ? q2 : q2 - c;
+        const bool from_wl = isw && q == c - 1;   // the W column this kernel wrote
+        const z64 *col = a.PXc + (int64_t)(isw ? kPL + q : q) * n;
         double sr = 0.0, si = 0.0;
-        for (int i = k + 1 + lane; i < n; i += 64) {
-            z64 u;
-            if (isw) u = q == c - 1 ? wl[i] : a.PX[(int64_t)i * 2 * kPL + kPL + q];
-            else u = a.PX[(int64_t)i * 2 * kPL + q];
-            const z64 pr = cmulc(al[i], u);   // conj(u) v
+        int i = k + 1 + lane;
+        for (; i + 192 < n; i += 256) {   // four rows per lane in flight
+            z64 u[4];
+#pragma unroll
+            for (int r = 0; r < 4; ++r) u[r] = from_wl ? wl[i + 64 * r] : col[i + 64 * r];
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const z64 pr = cmulc(al[i + 64 * r], u[r]);   // conj(u) v
+                sr += pr.re;
+                si += pr.im;
+            }
+        }
+        for (; i < n; i += 64) {
+            const z64 u = from_wl ? wl[i] : col[i];
+            const z64 pr = cmulc(al[i], u);
             sr += pr.re;
             si += pr.im;
         }
@@ -338,10 +374,10 @@ __global__ __launch_bounds__(1024) void k_chol_diag(z64 *G, int ld, int j0, int 
 // Scratch of the large-order routines (bytes), carved in the order below.
 size_t heev_large_scratch_bytes(int n, int nw) {
     const size_t zn = sizeof(z64);
-    return 16 * 256                                       // alignment of the 16 regions
+    return 17 * 256                                       // alignment of the 17 regions
            + (size_t)n * (2 * sizeof(double) + zn)        // d, e, tau
            + (size_t)n * n * zn                           // Vr
-           + (size_t)2 * n * 2 * kPL * zn                 // PX, PY
+           + (size_t)3 * n * 2 * kPL * zn                 // PX, PY, PXc
            + (size_t)2 * n * zn + 2 * kPL * zn            // vbuf, y, s
            + (size_t)n * n * sizeof(double)               // Z
            + (size_t)2 * kPL * kPL * zn                   // Gram, T
@@ -374,6 +410,7 @@ int heev_lowest_large(int n, z64 *A, int ld, int nw, double *w, z64 *coef, int l
     a.Vr = reinterpret_cast<z64 *>(take(sizeof(z64) * (size_t)n * n));
     a.PX = reinterpret_cast<z64 *>(take(sizeof(z64) * (size_t)n * 2 * kPL));
     a.PY = reinterpret_cast<z64 *>(take(sizeof(z64) * (size_t)n * 2 * kPL));
+    a.PXc = reinterpret_cast<z64 *>(take(sizeof(z64) * (size_t)n * 2 * kPL));
     a.vbuf = reinterpret_cast<z64 *>(take(sizeof(z64) * n));
     a.y = reinterpret_cast<z64 *>(take(sizeof(z64) * n));
     a.s = reinterpret_cast<z64 *>(take(sizeof(z64) * 2 * kPL));

@@ -233,9 +233,10 @@ __global__ __launch_bounds__(kRedThreads) void k_reduce_dapply(int M, int nsplit
 
 // ----------------------------------------------------------------- NN ------
 // C[j][g] = alpha * sum_i A[j][i] B[i][g] + beta * C[j][g]
-template <typename T, typename TC>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kGemmWaves))) void k_gemm_nn(int M, int G, int K, const cx<T> *__restrict__ A, int64_t lda,
-                                                 const cx<T> *__restrict__ B, int64_t ldb, cx<TC> *__restrict__ C,
+// TS is the type A and B are stored in; they are rounded to T while staged.
+template <typename T, typename TC, typename TS = T>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kGemmWaves))) void k_gemm_nn(int M, int G, int K, const cx<TS> *__restrict__ A, int64_t lda,
+                                                 const cx<TS> *__restrict__ B, int64_t ldb, cx<TC> *__restrict__ C,
                                                  int64_t ldc, double alpha, double beta) {
     __shared__ cx<T> As[TM][KP];
     __shared__ cx<T> Bs[KT][TN + 1];
@@ -258,13 +259,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kGemmWaves)
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
             const int gk = k0 + ak + q;
-            ra[q] = (gj < M && gk < K) ? A[gj * lda + gk] : cx<T>{T(0), T(0)};
+            ra[q] = (gj < M && gk < K) ? cvt<T>(A[gj * lda + gk]) : cx<T>{T(0), T(0)};
         }
         const int gk = k0 + bk;
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
             const int gg = g0 + bg + q;
-            rb[q] = (gk < K && gg < G) ? B[gk * ldb + gg] : cx<T>{T(0), T(0)};
+            rb[q] = (gk < K && gg < G) ? cvt<T>(B[gk * ldb + gg]) : cx<T>{T(0), T(0)};
         }
     };
     load(0);
@@ -446,15 +447,20 @@ int proj_dapply(int prec, int M, int N, int K, const void *Bm, int64_t ldb, cons
                                             chunk_hint, st);
 }
 
-template <typename T, typename TC>
+template <typename T, typename TC, typename TS = T>
 static int gemm_nn_t(int M, int G, int K, const void *A, int64_t lda, const void *B, int64_t ldb, void *C,
                      int64_t ldc, double alpha, double beta, hipStream_t st) {
     if (M <= 0 || G <= 0) return ABACUS_PW_OK;
     dim3 grid(ceil_div(M, TM), ceil_div(G, TN));
     KernelTimer kt("gemm_nn", st);
-    hipLaunchKernelGGL((k_gemm_nn<T, TC>), grid, dim3(256), 0, st, M, G, K, static_cast<const cx<T> *>(A), lda,
-                       static_cast<const cx<T> *>(B), ldb, static_cast<cx<TC> *>(C), ldc, alpha, beta);
+    hipLaunchKernelGGL((k_gemm_nn<T, TC, TS>), grid, dim3(256), 0, st, M, G, K, static_cast<const cx<TS> *>(A), lda,
+                       static_cast<const cx<TS> *>(B), ldb, static_cast<cx<TC> *>(C), ldc, alpha, beta);
     return check_launch("gemm_nn");
+}
+
+int gemm_nn_f32_of_f64(int M, int G, int K, const void *A, int64_t lda, const void *B, int64_t ldb, void *C,
+                       int64_t ldc, double alpha, double beta, hipStream_t st) {
+    return gemm_nn_t<float, double, double>(M, G, K, A, lda, B, ldb, C, ldc, alpha, beta, st);
 }
 
 int gemm_nn(int prec, int M, int G, int K, const void *A, int64_t lda, const void *B, int64_t ldb, void *C,

@@ -28,6 +28,12 @@ int gemm_cn_f32_of_f64(int M, int N, int K, const void *A, int64_t lda, const vo
 int gemm_nn(int prec, int M, int G, int K, const void *A, int64_t lda, const void *B, int64_t ldb, void *C,
             int64_t ldc, double alpha, double beta, hipStream_t st);
 
+// As gemm_nn on complex128 A, B and C with FP32 products: the operands are rounded to
+// complex64 as they are staged, C accumulates in FP64 (basis updates of the
+// reduced-precision Davidson phase).
+int gemm_nn_f32_of_f64(int M, int G, int K, const void *A, int64_t lda, const void *B, int64_t ldb, void *C,
+                       int64_t ldc, double alpha, double beta, hipStream_t st);
+
 // As gemm_nn with complex64 A and B accumulated into a complex128 C.
 int gemm_nn_f32_into_f64(int M, int G, int K, const void *A, int64_t lda, const void *B, int64_t ldb, void *C,
                          int64_t ldc, double alpha, double beta, hipStream_t st);
