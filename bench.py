@@ -75,6 +75,9 @@ def parse():
     ap.add_argument("--c4-davidson", action="store_true",
                     help="also run Davidson to a 1e-8 residual on the 128^3, 1024-band workload in FP64 and "
                          "MIXED_BF16 (several minutes)")
+    ap.add_argument("--cpu-extended", action="store_true",
+                    help="also time the oracle on C1, C2, C4 and C5 (H psi samples, C1 Davidson, C2 and C5 "
+                         "Davidson iterations; several minutes of host time)")
     ap.add_argument("--traffic-probe", action="store_true",
                     help="run a plain 256 MiB copy and a few FP64 H psi steps only (for counter collection)")
     ap.add_argument("--probe-workload", default=WORKLOAD,
@@ -242,6 +245,53 @@ def cpu_baseline(prob, one_thread_bands=1):
             "one_thread": {"value": one_thread_bands / t_one, "unit": "band-applies/s",
                            "sample": f"{one_thread_bands} band of k-point 0 on 1 thread ({t_one:.2f} s wall)"},
             "host": host_cpu()}
+
+
+def cpu_extended(W, max_iter_small=3):
+    """The oracle on the other workloads (opt-in: several minutes of host time): FP64 H psi
+    band-applies/s on a band sample of C1, C2, C4 and C5 (as many bands as OpenMP threads,
+    at the first k-point), the full Davidson of C1 to 1e-8, and seconds per Davidson
+    iteration at k-point 0 of C2 and C5 after a fixed number of iterations. C3 and C4
+    Davidson iterations are not timed: one iteration applies H to 512 or 1024 bands,
+    which the H psi rates above put at minutes per iteration."""
+    import oracle
+    nthreads = oracle.num_threads()
+    out = {"cores": nthreads, "kind": "oracle", "hpsi": {}, "davidson": {}}
+    for name in ("C1", "C2", "C4", "C5"):
+        prob = W.make_problem(name)
+        nbs = min(prob.nb, nthreads)
+        sub = oracle._single_k(prob, 0)
+        rows = np.ascontiguousarray(prob.psi_k(0)[:nbs]).reshape(-1)
+        t0 = time.perf_counter()
+        oracle.apply_h(sub, rows, nb=nbs)
+        dt = time.perf_counter() - t0
+        out["hpsi"][name] = {"band_applies_per_s": nbs / dt, "bands": nbs, "s": dt}
+        log(f"cpu extended: {name} H psi, {nbs} bands in {dt:.2f} s")
+        if name == "C1":
+            t0 = time.perf_counter()
+            eig, _, res, its = oracle.davidson(prob, tol=1e-8, max_iter=200)
+            dt = time.perf_counter() - t0
+            out["davidson"][name] = {"s_per_kpoint": dt / prob.nk, "iterations": [int(x) for x in its],
+                                     "max_resid": float(res.max()), "tol": 1e-8}
+            log(f"cpu extended: C1 Davidson {dt:.2f} s, {list(its)} iterations")
+        elif name in ("C2", "C5"):
+            x0 = np.asarray(prob.psi_k(0))
+
+            def hop(r, sub=sub):
+                return oracle.apply_h(sub, r.reshape(-1), nb=r.shape[0]).reshape(r.shape)
+
+            t0 = time.perf_counter()
+            oracle.davidson_k(hop, x0, oracle.kinetic(sub, 0), 1e-8, 0, 2)
+            t_start = time.perf_counter() - t0
+            t0 = time.perf_counter()
+            _, _, _, it = oracle.davidson_k(hop, x0, oracle.kinetic(sub, 0), 1e-8, max_iter_small, 2)
+            dt = time.perf_counter() - t0
+            per = (dt - t_start) / max(1, int(it))
+            out["davidson"][name] = {"s_start": t_start, "iterations": int(it), "s_per_iteration": per,
+                                     "k_point": 0}
+            log(f"cpu extended: {name} Davidson start {t_start:.1f} s, {per:.1f} s per iteration")
+        del prob
+    return out
 
 
 def measured_hbm_peak(dev, nbytes=1 << 30, reps=5):
@@ -452,6 +502,9 @@ def main():
     if not args.no_cpu:
         log("CPU baseline (oracle)")
         out["cpu_baseline"] = cpu_baseline(prob)
+        if args.cpu_extended:
+            log("CPU oracle on the other workloads")
+            out["cpu_baseline"]["other_workloads"] = cpu_extended(W)
     del x64, dp, prob
     torch.cuda.empty_cache()
     B.plan_reset()
