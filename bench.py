@@ -78,6 +78,9 @@ def parse():
     ap.add_argument("--cpu-extended", action="store_true",
                     help="also time the oracle on C1, C2, C4 and C5 (H psi samples, C1 Davidson, C2 and C5 "
                          "Davidson iterations; several minutes of host time)")
+    ap.add_argument("--c3-davidson", action="store_true",
+                    help="also run Davidson to a 1e-8 residual on the headline workload (8 k-points x 512 bands) "
+                         "in FP64 and MIXED_BF16 (about two minutes)")
     ap.add_argument("--traffic-probe", action="store_true",
                     help="run a plain 256 MiB copy and a few FP64 H psi steps only (for counter collection)")
     ap.add_argument("--probe-workload", default=WORKLOAD,
@@ -536,6 +539,9 @@ def main():
         if not args.no_cg:
             log("C2 CG")
             out["cg_vs_davidson"] = cg_times(B, W, dev, out.get("davidson"))
+    if args.c3_davidson:
+        log("C3 Davidson to 1e-8")
+        out["davidson_c3_full"] = davidson_times(B, W, dev, "C3", max_iter=300, modes=(("fp64", 0), ("mixed_bf16", 2)))
     if args.c4_davidson:
         log("C4 Davidson to 1e-8")
         out["davidson_c4"] = davidson_times(B, W, dev, "C4", max_iter=300, modes=(("fp64", 0), ("mixed_bf16", 2)))
