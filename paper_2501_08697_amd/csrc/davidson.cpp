@@ -49,17 +49,17 @@ struct HostLists {
     double *theta = nullptr;
     int n = 0;
     ~HostLists() {
-        if (act) (void)hipHostFree(act);
+        if (theta) (void)hipHostFree(theta);
     }
     int ensure(int m) {
         if (m <= n) return ABACUS_PW_OK;
-        if (act) APW_HIP(hipHostFree(act));
+        if (theta) APW_HIP(hipHostFree(theta));
         void *p = nullptr;
-        APW_HIP(hipHostMalloc(&p, (sizeof(int) * 3 + sizeof(double)) * (size_t)m, hipHostMallocDefault));
-        act = static_cast<int *>(p);
+        APW_HIP(hipHostMalloc(&p, (sizeof(double) + sizeof(int) * 3) * (size_t)m, hipHostMallocDefault));
+        theta = static_cast<double *>(p);   // the doubles first, so every array is aligned
+        act = reinterpret_cast<int *>(theta + m);
         keep = act + m;
         idx = keep + m;
-        theta = reinterpret_cast<double *>(idx + m);
         n = m;
         return ABACUS_PW_OK;
     }
