@@ -413,7 +413,10 @@ int abacus_pw_profile_read(char *buf, int size);
  *              two streams and join the second back into the caller's stream before the
  *              call returns, so stream semantics and graph capture are unchanged; 2 one stream
  * yz_threads   threads per work-group of the compact-row plane kernels (planes too large
- *              for LDS, one or two work-groups per CU): 256, 512 or 1024 (0 = library default, 1024)
+ *              for LDS, one or two work-groups per CU): 256, 512 or 1024 for both passes; 0 =
+ *              library default: 512 for the inverse pass, and for the forward pass a form whose
+ *              first transform phase loads the slab itself (512 threads) where that phase has
+ *              128 to 512 tasks, else 1024
  * Results do not depend on the knobs beyond rounding (the split-K chunk changes the
  * summation grouping of the projections). Returns EBAD_SHAPE for invalid values.
  */

@@ -581,6 +581,141 @@ __global__ __launch_bounds__(NT) void k_yz_fwd_c(const cx<T> *__restrict__ slab,
     }
 }
 
+template <int N, typename T, typename TIO, int NT>
+__global__ __launch_bounds__(NT) void k_yz_fwd_d(const cx<T> *__restrict__ slab, int nslab,
+                                                 const KDesc *__restrict__ kd, BatchArgs ba,
+                                                 const cx<T> *__restrict__ tw_g, const cx<TIO> *__restrict__ psi_all,
+                                                 cx<TIO> *__restrict__ hpsi_all, double inv_n, int bpw, int rows_max,
+                                                 int C) {
+    KDesc D;
+    int kk, b0, b1;
+    int s;
+    batch_block(kd, ba, bpw, D, kk, b0, b1, s);
+    const int *__restrict__ pt_off = D.pt_off, *__restrict__ pt_g = D.pt_g, *__restrict__ pt_pos = D.pt_pos;
+    const int *__restrict__ row_off = D.row_off, *__restrict__ row_list = D.row_list;
+    const double *__restrict__ kin = D.kin;
+    const int64_t koff = ba.nb_total * (D.pw_off - ba.off0) + (int64_t)ba.b0 * D.npw;
+    const cx<TIO> *psi = psi_all + koff;
+    cx<TIO> *hpsi = hpsi_all + koff;
+    const int64_t ld = D.npw;
+    slab += (int64_t)kk * ba.bbt * nslab * (int64_t)(N * N);
+    extern __shared__ __align__(16) unsigned char smem[];
+    cx<T> *rows = reinterpret_cast<cx<T> *>(smem);
+    cx<T> *ybuf = rows + rows_max * N;
+    cx<T> *tw = ybuf + N * C;
+    int *map = reinterpret_cast<int *>(tw + N);
+    const int tid = threadIdx.x;
+    const int r0 = row_off[s], nr = row_off[s + 1] - r0;
+    const int p0 = pt_off[s], p1 = pt_off[s + 1];
+    const TIO sc = static_cast<TIO>(inv_n);
+    constexpr int A = LdsSplit<N>::A, B = LdsSplit<N>::B;
+    for (int i = tid; i < N; i += NT) {
+        tw[i] = tw_g[i];
+        map[i] = -1;
+    }
+    __syncthreads();
+    for (int r = tid; r < nr; r += NT) map[row_list[r0 + r]] = r;
+    // the first phase of each chunk's forward y transform (task (c, jb): the A values at
+    // j2 = jb + B ja of column c0 + c) loads its values straight from the slab; the next
+    // chunk's (or the next band's first chunk's) are fetched while this one transforms
+    const int nchunk = (N + C - 1) / C;
+    cx<T> pre[A];
+    // slab offset of this thread's phase-1 column in chunk ci of band b (-1: no task)
+    auto col_of = [=](int b, int ci) -> int64_t {
+        const int c0 = ci * C, w = min(C, N - c0);
+        if (tid >= w * B) return -1;
+        const int c = tid % w, jb = tid / w;
+        return ((int64_t)b * nslab + s) * (int64_t)(N * N) + jb * N + c0 + c;
+    };
+    {
+        const int64_t o = col_of(b0, 0);
+#pragma unroll
+        for (int ja = 0; ja < A; ++ja) pre[ja] = o >= 0 ? slab[o + (int64_t)B * ja * N] : czero<T>();
+    }
+    // the plane's first MAXP * NT sphere points: psi index and compact-row position
+    constexpr int MAXP = NT >= 1024 ? 1 : 4;
+    int gi[MAXP], pos[MAXP];
+#pragma unroll
+    for (int q = 0; q < MAXP; ++q) {
+        const int p = p1 > p0 ? min(p0 + tid + q * NT, p1 - 1) : 0;
+        gi[q] = pt_g[p];
+        pos[q] = pt_pos[p];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < MAXP; ++q) {
+        const int slot = pos[q] / N;
+        pos[q] = p0 + tid + q * NT < p1 ? map[slot] * N + (pos[q] - slot * N) : -1;
+    }
+    for (int b = b0; b < b1; ++b) {
+        const cx<TIO> *x = psi + b * ld;
+        cx<TIO> *y = hpsi + b * ld;
+        for (int ci = 0; ci < nchunk; ++ci) {
+            const int c0 = ci * C, w = min(C, N - c0);
+            // phase 1, task (c, jb): forward DFT_A of natural j2 = jb + B ja, twiddle, to ybuf
+            // (one task per thread: w B <= C B <= NT, checked by the launcher)
+            if (tid < w * B) {
+                const int c = tid % w, jb = tid / w;
+                cx<T> a[A];
+#pragma unroll
+                for (int ja = 0; ja < A; ++ja) a[ja] = pre[ja];
+                const int nb_ = ci + 1 < nchunk ? b : b + 1, nc_ = ci + 1 < nchunk ? ci + 1 : 0;
+                const int64_t o = nb_ < b1 ? col_of(nb_, nc_) : -1;
+#pragma unroll
+                for (int ja = 0; ja < A; ++ja) pre[ja] = o >= 0 ? slab[o + (int64_t)B * ja * N] : czero<T>();
+                RegDft<A, -1, T>::run(a);
+                ybuf[jb * C + c] = a[0];
+#pragma unroll
+                for (int ka = 1; ka < A; ++ka) ybuf[(jb + B * ka) * C + c] = cmulc(a[ka], tw[jb * A + ka]);
+            } else if (ci + 1 == nchunk && b + 1 < b1) {
+                // threads without a task in this chunk may have one in the next band's first chunk
+                const int64_t o = col_of(b + 1, 0);
+#pragma unroll
+                for (int ja = 0; ja < A; ++ja) pre[ja] = o >= 0 ? slab[o + (int64_t)B * ja * N] : czero<T>();
+            }
+            __syncthreads();
+            // phase 2, task (c, ka): forward DFT_B of slots B ka + jb; output slot B ka + kb
+            // goes to its compact row when the plane has one there
+            for (int t = tid; t < w * A; t += NT) {
+                const int c = t % w, ka = t / w;
+                cx<T> z[B];
+#pragma unroll
+                for (int jb = 0; jb < B; ++jb) z[jb] = ybuf[(B * ka + jb) * C + c];
+                RegDft<B, -1, T>::run(z);
+#pragma unroll
+                for (int kb = 0; kb < B; ++kb) {
+                    const int r = map[B * ka + kb];
+                    if (r >= 0) rows[r * N + c0 + c] = z[kb];
+                }
+            }
+            __syncthreads();
+        }
+        // this band's psi and |k+G|^2 at the thread's points, fetched behind the z transforms
+        cx<TIO> xq[MAXP];
+        TIO kq[MAXP];
+#pragma unroll
+        for (int q = 0; q < MAXP; ++q) {
+            xq[q] = x[gi[q]];
+            kq[q] = static_cast<TIO>(kin[gi[q]]);
+        }
+        lds_fft<N, -1, false>(rows, nr, [](int l) { return l * N; }, 1, tw);
+#pragma unroll
+        for (int q = 0; q < MAXP; ++q)
+            if (pos[q] >= 0) {
+                const cx<TIO> v = cvt<TIO>(rows[pos[q]]);
+                y[gi[q]] = cx<TIO>{kq[q] * xq[q].re + sc * v.re, kq[q] * xq[q].im + sc * v.im};
+            }
+        for (int p = p0 + MAXP * NT + tid; p < p1; p += NT) {
+            const int g = pt_g[p], ps = pt_pos[p], slot = ps / N;
+            const cx<TIO> v = cvt<TIO>(rows[map[slot] * N + (ps - slot * N)]);
+            const TIO kg = static_cast<TIO>(kin[g]);
+            const cx<TIO> xg = x[g];
+            y[g] = cx<TIO>{kg * xg.re + sc * v.re, kg * xg.im + sc * v.im};
+        }
+        __syncthreads();
+    }
+}
+
 // Adjoint of the local term with respect to V: for one (j2, j3 tile) and the
 // contiguous band range [g bpw, (g + 1) bpw) of the batch, inverse x transforms
 // of the psi and dY planes and acc(r) += Re(conj(gamma_b(r)) psi_b(r)); part[g]
@@ -815,7 +950,10 @@ static int launch_yz(bool inverse, const Plan &P, int k0, int nkb, const BatchAr
         const size_t lds = compact_lds<N, T>(P.max_rows, Cc);
         // threads per work-group: the compact planes hold one or two work-groups per
         // CU, so more waves per group hide more of the memory latency
-        const int nt = g_yz_threads > 0 ? g_yz_threads : 1024;   // 1024 measured 1.5x faster than 256 at 128^3 FP64
+        // default: 512 threads for the inverse pass (6% faster than 1024 at 120^3 FP64), and for
+        // the forward pass the direct form below where its first phase has 128 to 512 tasks,
+        // else 1024 threads (1024 measured 1.5x faster than 256 at 128^3 FP64)
+        const int nt = g_yz_threads > 0 ? g_yz_threads : (inverse ? 512 : 1024);
         const int sel = nt == 256 ? 0 : (nt == 512 ? 1 : 2);
         auto inv = sel == 0 ? k_yz_inv_c<N, T, TIO, 256> : (sel == 1 ? k_yz_inv_c<N, T, TIO, 512> : k_yz_inv_c<N, T, TIO, 1024>);
         auto fwd = sel == 0 ? k_yz_fwd_c<N, T, TIO, 256> : (sel == 1 ? k_yz_fwd_c<N, T, TIO, 512> : k_yz_fwd_c<N, T, TIO, 1024>);
@@ -837,6 +975,21 @@ static int launch_yz(bool inverse, const Plan &P, int k0, int nkb, const BatchAr
             once[sel] = true;
         }
         KernelTimer kt("yz_fwd", st);
+        // the direct forward pass: its first phase loads the slab itself (one barrier less
+        // per chunk); at 120^3 FP64 (16 columns x 8 tasks) it took the pass from 3.87 to
+        // 3.12 ms, at 128^3 (8 x 8 tasks) it is no faster
+        const int tasks1 = Cc * LdsSplit<N>::B;
+        if (g_yz_threads == 0 && tasks1 >= 128 && tasks1 <= 512) {
+            static bool once_d = false;
+            if (!once_d) {
+                APW_TRY(allow_lds(k_yz_fwd_d<N, T, TIO, 512>, kLdsLimit));
+                once_d = true;
+            }
+            hipLaunchKernelGGL((k_yz_fwd_d<N, T, TIO, 512>), grid, dim3(512), lds, st, static_cast<const cx<T> *>(slab),
+                               P.nslab, kd, ba, tw, static_cast<const cx<TIO> *>(psi), static_cast<cx<TIO> *>(hpsi),
+                               1.0 / (double)P.N, bpw, P.max_rows, Cc);
+            return check_launch("yz_fwd_d");
+        }
         hipLaunchKernelGGL(fwd, grid, block, lds, st, static_cast<const cx<T> *>(slab), P.nslab, kd, ba, tw,
                            static_cast<const cx<TIO> *>(psi), static_cast<cx<TIO> *>(hpsi), 1.0 / (double)P.N, bpw,
                            P.max_rows, Cc);
