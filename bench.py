@@ -997,6 +997,34 @@ def davidson_iteration_times(B, dev, prob, dp, iters=3):
         out[name] = {"s_per_iteration_per_kpoint": (t[1] - t[0]) / (iters * prob.nk),
                      "s_start_per_kpoint": t[0] / prob.nk}
         log(f"Davidson iterations {name}: {out[name]}")
+    # the subspace products of the FP64 iterations (projections, orthogonalisation, Ritz
+    # updates, Cholesky-QR and Rayleigh-Ritz GEMMs, "subspace:" records of the library's
+    # profile with their counted flops), from two profiled solves differenced like the times
+    recs = []
+    for n in (0, iters):
+        x = torch.from_numpy(prob.psi).to(dev)
+        B.profile_read()
+        B.profile_enable(True)
+        B.davidson(dp, x, tol=1e-30, max_iter=n, precision=B.FP64)
+        B.profile_enable(False)
+        recs.append(B.profile_read(flops=True))
+        del x
+    per = float(iters * prob.nk)
+    sub = {}
+    for lab in sorted(set(recs[0]) | set(recs[1])):
+        a, b_ = recs[0].get(lab, (0, 0.0, 0.0)), recs[1].get(lab, (0, 0.0, 0.0))
+        ms, fl = (b_[1] - a[1]) / per, (b_[2] - a[2]) / per
+        sub[lab] = {"ms_per_iteration_per_kpoint": ms}
+        if fl > 0 and ms > 0:
+            tf = fl / (ms * 1e-3) / 1e12
+            sub[lab].update({"tflops_counted": tf, "tflops_executed": 0.75 * tf, "frac_executed_fp64": 0.75 * tf / 78.6})
+    gemm = [sub[k] for k in ("subspace:gemm_cn", "subspace:gemm_nn") if k in sub and "tflops_counted" in sub[k]]
+    if gemm:
+        tot_ms = sum(g["ms_per_iteration_per_kpoint"] for g in gemm)
+        tot_tf = sum(g["tflops_counted"] * g["ms_per_iteration_per_kpoint"] for g in gemm) / tot_ms
+        out["fp64_subspace_gemm"] = {"ms_per_iteration_per_kpoint": tot_ms, "tflops_counted": tot_tf,
+                                     "tflops_executed": 0.75 * tot_tf, "frac_executed_fp64": 0.75 * tot_tf / 78.6}
+    out["fp64_profile_per_iteration"] = sub
     return out
 
 if __name__ == "__main__":

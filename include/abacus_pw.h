@@ -391,9 +391,12 @@ int abacus_pw_plan_reset(void);
  * Optional per-kernel timing. When enabled, the library records a pair of HIP
  * events around every kernel it enqueues, on the stream it enqueues it on, and
  * accumulates elapsed time per kernel name at the next abacus_pw_profile_read.
- * abacus_pw_profile_read synchronises, then writes up to max_entries records
- * "name\tlaunches\ttotal_ms\n" into buf (NUL-terminated); returns the number of
- * records, or a negative code.
+ * abacus_pw_profile_read synchronises, then writes the records
+ * "name\tlaunches\ttotal_ms\tflops\n" into buf (NUL-terminated, truncated to size);
+ * returns the number of records, or a negative code. Kernels enqueued by the Davidson
+ * solver for its subspace (projections, orthogonalisation, Ritz updates, Cholesky-QR and
+ * Rayleigh-Ritz products) are named "subspace:<kernel>" and carry their flop count
+ * (complex products as 8 M N K); other records carry 0 flops.
  */
 int abacus_pw_profile_enable(int on);
 int abacus_pw_profile_read(char *buf, int size);

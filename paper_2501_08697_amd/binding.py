@@ -437,12 +437,16 @@ def profile_enable(on: bool = True):
     check(lib().abacus_pw_profile_enable(1 if on else 0))
 
 
-def profile_read() -> dict:
-    """{kernel name: (launches, total_ms)} accumulated since the last read."""
+def profile_read(flops: bool = False) -> dict:
+    """{kernel name: (launches, total_ms)} accumulated since the last read, or with
+    flops=True (launches, total_ms, flops), the flops counted for the record (the
+    Davidson subspace products, "subspace:<kernel>"; 0 elsewhere)."""
     buf = C.create_string_buffer(1 << 16)
     check(lib().abacus_pw_profile_read(buf, 1 << 16))
     out = {}
     for line in buf.value.decode().splitlines():
-        name, n, ms = line.split("\t")
-        out[name] = (int(n), float(ms))
+        f = line.split("\t")
+        n, ms = int(f[1]), float(f[2])
+        fl = float(f[3]) if len(f) > 3 else 0.0
+        out[f[0]] = (n, ms, fl) if flops else (n, ms)
     return out

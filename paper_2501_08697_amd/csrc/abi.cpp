@@ -26,16 +26,25 @@ int set_error(int code, const std::string &msg) {
 
 // ----------------------------------------------------------------- timing --
 bool g_prof_on = false;
+thread_local const char *t_prof_scope = nullptr;
 namespace {
 struct Pending {
-    const char *name;
+    std::string name;
     hipEvent_t a, b;
+};
+struct Total {
+    long n = 0;
+    double ms = 0.0, flops = 0.0;
 };
 std::mutex g_prof_mu;
 std::vector<Pending> g_pending;
 std::vector<hipEvent_t> g_pool;
-thread_local std::vector<std::pair<const char *, hipEvent_t>> t_open;
-std::map<std::string, std::pair<long, double>> g_totals;
+thread_local std::vector<std::pair<std::string, hipEvent_t>> t_open;
+std::map<std::string, Total> g_totals;
+
+std::string scoped(const char *name) {
+    return t_prof_scope ? std::string(t_prof_scope) + ":" + name : std::string(name);
+}
 
 hipEvent_t take_event() {
     std::lock_guard<std::mutex> l(g_prof_mu);
@@ -53,7 +62,7 @@ hipEvent_t take_event() {
 void prof_begin(const char *name, hipStream_t s) {
     hipEvent_t e = take_event();
     (void)hipEventRecord(e, s);
-    t_open.emplace_back(name, e);
+    t_open.emplace_back(scoped(name), e);
 }
 
 void prof_end(hipStream_t s) {
@@ -63,7 +72,13 @@ void prof_end(hipStream_t s) {
     hipEvent_t b = take_event();
     (void)hipEventRecord(b, s);
     std::lock_guard<std::mutex> l(g_prof_mu);
-    g_pending.push_back(Pending{name, a, b});
+    g_pending.push_back(Pending{std::move(name), a, b});
+}
+
+void prof_count_flops(const char *name, double flops) {
+    if (!g_prof_on) return;
+    std::lock_guard<std::mutex> l(g_prof_mu);
+    g_totals[scoped(name)].flops += flops;
 }
 
 static int prof_collect() {
@@ -78,8 +93,8 @@ static int prof_collect() {
         APW_HIP(hipEventElapsedTime(&ms, p.a, p.b));
         std::lock_guard<std::mutex> l(g_prof_mu);
         auto &t = g_totals[p.name];
-        t.first += 1;
-        t.second += ms;
+        t.n += 1;
+        t.ms += ms;
         g_pool.push_back(p.a);
         g_pool.push_back(p.b);
     }
@@ -169,9 +184,9 @@ int abacus_pw_profile_read(char *buf, int size) {
         {
             std::lock_guard<std::mutex> l(g_prof_mu);
             for (auto &kv : g_totals) {
-                char line[256];
-                std::snprintf(line, sizeof line, "%s\t%ld\t%.6f\n", kv.first.c_str(), kv.second.first,
-                              kv.second.second);
+                char line[320];
+                std::snprintf(line, sizeof line, "%s\t%ld\t%.6f\t%.6e\n", kv.first.c_str(), kv.second.n,
+                              kv.second.ms, kv.second.flops);
                 out += line;
                 ++n;
             }

@@ -64,7 +64,18 @@ int set_error(int code, const std::string &msg);
 // ---------------------------------------------------------------------------
 void prof_begin(const char *name, hipStream_t s);
 void prof_end(hipStream_t s);
+// flops (complex products counted as 8 M N K) attributed to the label `name` in the
+// current scope, for the kernels enqueued under that label
+void prof_count_flops(const char *name, double flops);
 extern bool g_prof_on;
+// Records made while a ProfScope is alive are labelled "scope:name" (innermost scope;
+// a null scope restores plain names), so one kernel can be reported per caller.
+extern thread_local const char *t_prof_scope;
+struct ProfScope {
+    const char *prev;
+    explicit ProfScope(const char *scope) : prev(t_prof_scope) { t_prof_scope = scope; }
+    ~ProfScope() { t_prof_scope = prev; }
+};
 
 struct KernelTimer {
     hipStream_t s;

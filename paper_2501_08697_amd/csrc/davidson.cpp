@@ -65,6 +65,16 @@ struct HostLists {
     }
 };
 
+// The dense subspace steps under their own profile names ("eigensolver:", "cholesky:"),
+// so that the "subspace:" records hold only the counted products.
+int potrf_inv_s(int n, z64 *G, int ld, z64 *Li, int ldi, int *info, void *scratch, hipStream_t st) {
+    ProfScope ps("cholesky");
+    return potrf_inv(n, G, ld, Li, ldi, info, scratch, st);
+}
+
+// Flops of a subspace product (complex, 8 M N K) for the per-kernel profile.
+void sub_flops(const char *label, double M, double N, double K) { prof_count_flops(label, 8.0 * M * N * K); }
+
 // Enqueue an upload from pinned host memory (no wait).
 int h2d_async(void *dst, const void *src, size_t bytes, hipStream_t st) {
     APW_HIP(hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, st));
@@ -93,7 +103,9 @@ int d2d(void *dst, const void *src, size_t bytes, hipStream_t st) {
 int cholqr_pass_async(int m, int npw, const z64 *T, z64 *Y, Buffers &b, int *info_dev, hipStream_t st) {
     z64 *G = b.G.as<z64>(), *Linv = b.Linv.as<z64>();
     APW_TRY(gemm_cn(0, m, m, npw, T, npw, T, npw, G, m, 1.0, 0.0, b.part.ptr, 0, st));
-    APW_TRY(potrf_inv(m, G, m, Linv, m, info_dev, b.chol.ptr, st));
+    sub_flops("gemm_cn", m, m, npw);
+    APW_TRY(potrf_inv_s(m, G, m, Linv, m, info_dev, b.chol.ptr, st));
+    sub_flops("gemm_nn", m, npw, m);
     return gemm_nn(0, m, npw, m, Linv, m, T, npw, Y, npw, 1.0, 0.0, st);
 }
 
@@ -104,7 +116,8 @@ int cholqr_rows(int m, int npw, z64 *T, z64 *Y, Buffers &b, int passes, hipStrea
     z64 *G = b.G.as<z64>(), *Linv = b.Linv.as<z64>();
     for (int pass = 0; pass < passes; ++pass) {
         APW_TRY(gemm_cn(0, m, m, npw, T, npw, T, npw, G, m, 1.0, 0.0, b.part.ptr, 0, st));
-        APW_TRY(potrf_inv(m, G, m, Linv, m, b.info.as<int>(), b.chol.ptr, st));
+        sub_flops("gemm_cn", m, m, npw);
+        APW_TRY(potrf_inv_s(m, G, m, Linv, m, b.info.as<int>(), b.chol.ptr, st));
         int info = 0;
         APW_TRY(d2h(&info, b.info.ptr, sizeof(int), st));
         if (info != 0) {
@@ -115,14 +128,16 @@ int cholqr_rows(int m, int npw, z64 *T, z64 *Y, Buffers &b, int passes, hipStrea
             for (double x : nrm) tr += x;
             const double shift = 11.0 * ((double)m * npw + (double)m * (m + 1)) * 2.220446049250313e-16 * tr;
             APW_TRY(gemm_cn(0, m, m, npw, T, npw, T, npw, G, m, 1.0, 0.0, b.part.ptr, 0, st));
+            sub_flops("gemm_cn", m, m, npw);
             APW_TRY(dav_add_diag(m, G, m, shift, st));
-            APW_TRY(potrf_inv(m, G, m, Linv, m, b.info.as<int>(), b.chol.ptr, st));
+            APW_TRY(potrf_inv_s(m, G, m, Linv, m, b.info.as<int>(), b.chol.ptr, st));
             APW_TRY(d2h(&info, b.info.ptr, sizeof(int), st));
             if (info != 0) return set_error(ABACUS_PW_ECHOLESKY, "Gram matrix is not positive definite");
             ++passes;   // a shifted pass is followed by one more plain pass
             if (passes > 4) passes = 4;
         }
         APW_TRY(gemm_nn(0, m, npw, m, Linv, m, T, npw, Y, npw, 1.0, 0.0, st));
+        sub_flops("gemm_nn", m, npw, m);
         APW_TRY(d2d(T, Y, sizeof(z64) * (size_t)m * npw, st));
     }
     return ABACUS_PW_OK;
@@ -134,10 +149,15 @@ int cholqr_rows(int m, int npw, z64 *T, z64 *Y, Buffers &b, int passes, hipStrea
 // orthonormal set to O(1e-17). Returns the coefficient rows (ld nmax) in *out.
 int rayleigh_ritz(int n, int nb, int nmax, Buffers &b, z64 **out, hipStream_t st) {
     z64 *Hw = b.Hw.as<z64>(), *coef = b.coef.as<z64>(), *G = b.G.as<z64>();
-    APW_TRY(heev_lowest(n, Hw, nmax, nb, b.theta.as<double>(), coef, nmax, b.heev.ptr, st));
+    {
+        ProfScope ps("eigensolver");
+        APW_TRY(heev_lowest(n, Hw, nmax, nb, b.theta.as<double>(), coef, nmax, b.heev.ptr, st));
+    }
     APW_TRY(gemm_cn(0, nb, nb, n, coef, nmax, coef, nmax, G, nb, 1.0, 0.0, b.part.ptr, 0, st));
+    sub_flops("gemm_cn", nb, nb, n);
     APW_TRY(dav_lowdin(nb, G, st));
     APW_TRY(gemm_nn(0, nb, n, nb, G, nb, coef, nmax, Hw, nmax, 1.0, 0.0, st));
+    sub_flops("gemm_nn", nb, n, nb);
     *out = Hw;
     return ABACUS_PW_OK;
 }
@@ -159,6 +179,7 @@ struct Result {
 int davidson_k(const abacus_pw_problem &p, Plan &P, int k, int hprec, int nb, z64 *X, Buffers &b, HostLists &hl,
                double tol, int max_iter, int ndim, int stagnation, std::vector<double> &theta_h,
                std::vector<double> &rn_h, Result &res, hipStream_t st) {
+    ProfScope prof_scope("subspace");   // per-kernel profile: this solver's own kernels
     const int npw = P.k[k].npw, nmax = ndim * nb;
     const double *kin = P.k[k].kin;
     if (nmax > kMaxSub) return set_error(ABACUS_PW_EBAD_SHAPE, "ndim * nb exceeds the device eigensolver limit (4096)");
@@ -197,12 +218,16 @@ int davidson_k(const abacus_pw_problem &p, Plan &P, int k, int hprec, int nb, z6
     // 1. Cholesky-QR, H X, Rayleigh-Ritz on span(X)
     APW_TRY(d2d(Xc, X, vb * nb, st));
     APW_TRY(cholqr_rows(nb, npw, Xc, Y, b, 1, st));
-    APW_TRY(apply_h_k(p, P, k, hprec, nb, Xc, Wc, st, false));
+    {
+        ProfScope hs(nullptr);   // H psi keeps the plain kernel names
+        APW_TRY(apply_h_k(p, P, k, hprec, nb, Xc, Wc, st, false));
+    }
     // subspace projections V^H (H V): FP32 products in a reduced-precision phase, else FP64
     // subspace projections V^H (H V): FP64, or in the reduced-precision phase FP32 (MIXED_FP32) or
     // bf16 (MIXED_BF16) products with FP32 accumulation
     if (hprec == ABACUS_PW_MIXED_BF16) APW_TRY(b.bfs.ensure(gemm_cn_bf16_of_f64_bytes(nmax, nb, npw)));
     auto project = [&](int M, int N, const z64 *A, const z64 *B, z64 *Cout, int ldc) -> int {
+        sub_flops(hprec == ABACUS_PW_MIXED_BF16 ? "gemm_cn_bf16" : "gemm_cn", M, N, npw);
         if (hprec == ABACUS_PW_FP64) return gemm_cn(0, M, N, npw, A, npw, B, npw, Cout, ldc, 1.0, 0.0, b.part.ptr, 0, st);
         if (hprec == ABACUS_PW_MIXED_BF16)
             return gemm_cn_bf16_of_f64(M, N, npw, A, npw, B, npw, Cout, ldc, b.bfs.ptr, st);
@@ -215,11 +240,13 @@ int davidson_k(const abacus_pw_problem &p, Plan &P, int k, int hprec, int nb, z6
     // 72^3 rose from 39 to 68. Cholesky-QR and the residuals stay FP64.
     const bool low = hprec == ABACUS_PW_MIXED_BF16;
     auto basis_cn = [&](int M, int N, const z64 *A, const z64 *B, z64 *Cout, int ldc) -> int {
+        sub_flops("gemm_cn", M, N, npw);
         return low ? gemm_cn_f32_of_f64(M, N, npw, A, npw, B, npw, Cout, ldc, 1.0, 0.0, b.part.ptr, 0, st)
                    : gemm_cn(0, M, N, npw, A, npw, B, npw, Cout, ldc, 1.0, 0.0, b.part.ptr, 0, st);
     };
     auto basis_nn = [&](int M, int K, const z64 *A, int lda, const z64 *B, z64 *Cout, double alpha,
                         double beta) -> int {
+        sub_flops("gemm_nn", M, npw, K);
         return low ? gemm_nn_f32_of_f64(M, npw, K, A, lda, B, npw, Cout, npw, alpha, beta, st)
                    : gemm_nn(0, M, npw, K, A, lda, B, npw, Cout, npw, alpha, beta, st);
     };
@@ -230,6 +257,7 @@ int davidson_k(const abacus_pw_problem &p, Plan &P, int k, int hprec, int nb, z6
     APW_TRY(rayleigh_ritz(nb, nb, nmax, b, &rc, st));
     APW_TRY(gemm_nn(0, nb, npw, nb, rc, nmax, Xc, npw, V, npw, 1.0, 0.0, st));
     APW_TRY(gemm_nn(0, nb, npw, nb, rc, nmax, Wc, npw, HV, npw, 1.0, 0.0, st));
+    sub_flops("gemm_nn", 2.0 * nb, npw, nb);
     APW_TRY(d2d(Xc, V, vb * nb, st));
     APW_TRY(d2d(Wc, HV, vb * nb, st));
     APW_TRY(dav_hs_diag(nb, theta, Hs, nmax, st));
@@ -359,7 +387,10 @@ int davidson_k(const abacus_pw_problem &p, Plan &P, int k, int hprec, int nb, z6
             APW_TRY(d2d(T, Y, vb * m, st));
             check_info2 = true;
         }
-        APW_TRY(apply_h_k(p, P, k, hprec, m, T, HT, st, false));
+        {
+            ProfScope hs(nullptr);
+            APW_TRY(apply_h_k(p, P, k, hprec, m, T, HT, st, false));
+        }
         const int n = nbasis + m;
         APW_TRY(project(n, m, Vb, HT, C, n));
         APW_TRY(dav_hs_append(nbasis, m, C, n, Hs, nmax, st));
