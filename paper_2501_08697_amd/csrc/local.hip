@@ -185,16 +185,35 @@ __global__ __launch_bounds__(256) void k_xpass(cx<T> *__restrict__ slab, int nsl
         const int sl = has_ka ? r2s[B * ka + kb] : -1;
         src[kb] = sl >= 0 ? (int)(sl * plane) : -1;
     }
-    cx<T> pre[B];
+    // phase-I values in flight: the next band's, and at N1 >= 120 also the one after
+    // (there the lines are long and few work-groups fit a CU, so one band of lookahead
+    // left the loads exposed; the second costs 32 VGPRs, which the shorter lengths
+    // would pay with a wave per SIMD)
+    constexpr bool kDeep = N1 >= 120;
+    cx<T> pre[B], pre2[kDeep ? B : 1];
 #pragma unroll
     for (int kb = 0; kb < B; ++kb) pre[kb] = (has_ka && src[kb] >= 0) ? base[b0 * bstride + src[kb]] : czero<T>();
+    if constexpr (kDeep) {
+#pragma unroll
+        for (int kb = 0; kb < B; ++kb)
+            pre2[kb] = (has_ka && src[kb] >= 0 && b0 + 1 < b1) ? base[(b0 + 1) * bstride + src[kb]] : czero<T>();
+    }
     for (int b = b0; b < b1; ++b) {
         if (has_ka) {
             cx<T> z[B];
 #pragma unroll
             for (int kb = 0; kb < B; ++kb) z[kb] = pre[kb];
-            // the next band's values are fetched now, behind phases F and O
-            if (b + 1 < b1) {
+            if constexpr (kDeep) {
+                // the band after next is fetched now, behind phases F and O of this band and the next
+#pragma unroll
+                for (int kb = 0; kb < B; ++kb) pre[kb] = pre2[kb];
+                if (b + 2 < b1) {
+#pragma unroll
+                    for (int kb = 0; kb < B; ++kb)
+                        if (src[kb] >= 0) pre2[kb] = base[(b + 2) * bstride + src[kb]];
+                }
+            } else if (b + 1 < b1) {
+                // the next band's values are fetched now, behind phases F and O
 #pragma unroll
                 for (int kb = 0; kb < B; ++kb)
                     if (src[kb] >= 0) pre[kb] = base[(b + 1) * bstride + src[kb]];
