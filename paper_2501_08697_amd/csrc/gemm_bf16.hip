@@ -83,14 +83,16 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
     // loader: row tid / 2 of each tile, k half (tid % 2) * 16 of the stage
     const int lr = tid >> 1, lh = (tid & 1) * 16;
     const bool arow = i0 + lr < M, brow = j0 + lr < N;
+    // a loader row past M (N) reads row 0 instead: such a row only feeds outputs with
+    // i >= M (j >= N), which are never stored, and the loads need no per-row branch
     const uint32_t *ga = A + (int64_t)(arow ? i0 + lr : 0) * lda + lh;
     const uint32_t *gb = B + (int64_t)(brow ? j0 + lr : 0) * ldb + lh;
     u4 pa[4], pb[4];
     auto fetch = [&](int k0) {
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-            pa[q] = arow ? *reinterpret_cast<const u4 *>(ga + k0 + 4 * q) : u4{0u, 0u, 0u, 0u};
-            pb[q] = brow ? *reinterpret_cast<const u4 *>(gb + k0 + 4 * q) : u4{0u, 0u, 0u, 0u};
+            pa[q] = *reinterpret_cast<const u4 *>(ga + k0 + 4 * q);
+            pb[q] = *reinterpret_cast<const u4 *>(gb + k0 + 4 * q);
         }
     };
     f4 cre[4][4], cim[4][4];
