@@ -80,14 +80,26 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kGemmWaves)
         for (int b = 0; b < 2; ++b) c1[a][b] = c2[a][b] = c3[a][b] = Acc<T>::zero();
     const int lr = tid >> 2, lk = (tid & 3) * 4;   // loader: row, first k of 4
     const int wi = (w & 1) * 32, wj = (w >> 1) * 32;
-    const int gi = i0 + lr, gj = j0 + lr;
+    // loader rows past M (N) read the last row instead: they only feed outputs that are
+    // never stored, and a whole stage then loads with no per-load branch (only the k tail
+    // of a chunk is bounded, and zero-filled, since it enters every sum)
+    const cx<TS> *ga = A + (int64_t)min(i0 + lr, M - 1) * lda + lk;
+    const cx<TS> *gb = B + (int64_t)min(j0 + lr, N - 1) * ldb + lk;
     cx<T> ra[4], rb[4];
     auto load = [&](int k0) {
+        if (k0 + KT <= ke) {
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const int gk = k0 + lk + q;
-            ra[q] = (gi < M && gk < ke) ? cvt<T>(A[gi * lda + gk]) : cx<T>{T(0), T(0)};
-            rb[q] = (gj < N && gk < ke) ? cvt<T>(B[gj * ldb + gk]) : cx<T>{T(0), T(0)};
+            for (int q = 0; q < 4; ++q) {
+                ra[q] = cvt<T>(ga[k0 + q]);
+                rb[q] = cvt<T>(gb[k0 + q]);
+            }
+        } else {
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const bool in = k0 + lk + q < ke;
+                ra[q] = in ? cvt<T>(ga[k0 + q]) : cx<T>{T(0), T(0)};
+                rb[q] = in ? cvt<T>(gb[k0 + q]) : cx<T>{T(0), T(0)};
+            }
         }
     };
     load(kb);
