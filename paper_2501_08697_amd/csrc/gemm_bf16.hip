@@ -118,14 +118,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
             *reinterpret_cast<u4 *>(&Bim[o]) = im[0];
             *reinterpret_cast<u4 *>(&Bim[o + 4]) = im[1];
         }
-        // the next stage's loads, in flight while this stage computes. The accumulation
-        // (kIntoF64, 72 stages of 32 projectors per tile at 2304 projectors) issues them before
-        // the barrier, so that the wait for the other waves' LDS writes also covers their
-        // latency: 4.96 -> 4.74 ms at 1024 bands x 161k PW. The projection, whose tiles run
-        // through long split-K chunks, measured 3.87 -> 4.08 ms that way and issues them after.
-        if (kIntoF64 && k0 + BK2 < ke) fetch(k0 + BK2);
+        // the next stage's loads, in flight while this stage computes, go out before the
+        // barrier, so that the wait for the other waves' LDS writes also covers their latency
+        // (at 1024 bands x 161k PW x 2304 projectors: accumulation 4.96 -> 4.74 ms, projection
+        // 3.39 -> 3.34 ms)
+        if (k0 + BK2 < ke) fetch(k0 + BK2);
         __syncthreads();
-        if (!kIntoF64 && k0 + BK2 < ke) fetch(k0 + BK2);
         bf8 br[4], bi[4];
 #pragma unroll
         for (int c = 0; c < 4; ++c) {
